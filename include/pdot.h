@@ -1,0 +1,185 @@
+/*
+ * pdot.h -- C ABI of the MI355X (gfx950) restarted-PDHG optimal-transport library.
+ *
+ * The library solves the discrete Kantorovich problem (Lu & Yang, "PDOT", arXiv
+ * 2407.19689, Section 1, eq. ot)
+ *
+ *     min <C, X>   s.t.   X 1_n = f,   X^T 1_m = g,   X >= 0
+ *
+ * with restarted PDHG in the matrix-free form of Algorithm 2 (alg:rpd): per iteration a
+ * projected primal step X+ = max(0, X - tau (C - p 1^T - 1 q^T)), the row and column sums
+ * of 2X+ - X, the dual steps p+ = p + sigma (f - (2X+ - X) 1), q+ = q + sigma (g -
+ * (2X+ - X)^T 1), and a running average.  Control follows Section 5: restart to the
+ * candidate of lower relative KKT error with the three restart conditions, the adaptive
+ * step size eta with tau = eta/omega and sigma = eta*omega, the primal-weight update at
+ * restarts, and termination on relative KKT error (Section 5.1, "Termination criteria").
+ * The KKT error is the stacked 2-norm of Section 3.1 (display after Algorithm 2); the
+ * relative form and the other readings of the text are listed with ot_params below.
+ *
+ * Every iteration runs on the GPU in hand-written HIP kernels; the host only launches
+ * graphs of iteration slots and reads a status word between them.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are row-major.  X_ij is transported mass from source i to target j.
+ *   - Input pointers may be host or device pointers (unified addressing); they are read
+ *     during the call only.  The caller owns every buffer it passes; the library never
+ *     frees or retains caller memory.
+ *   - The library allocates its own device workspace for the duration of a call unless
+ *     a workspace of at least ot_workspace_size() bytes is passed.
+ *   - Calls are ordered on the HIP stream passed as `stream` (hipStream_t, may be NULL
+ *     for an internal stream) and are synchronous: they return when results are in the
+ *     output buffers.
+ *   - Return value: OT_OK, or an error code; ot_last_error() then holds a message
+ *     (per thread).  OT_NOT_CONVERGED still fills every output with the returned iterate.
+ */
+#ifndef PDOT_H
+#define PDOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OT_OK = 0,
+    OT_ERR_INVALID = 1,    /* bad sizes, pointers, non-finite data, sum f != sum g, tol <= 0 */
+    OT_ERR_OOM = 2,        /* device allocation failed or workspace too small             */
+    OT_ERR_DEVICE = 3,     /* a HIP runtime call failed                                    */
+    OT_NOT_CONVERGED = 4,  /* iteration, pass or time limit reached; outputs are filled    */
+    OT_ERR_NUMERIC = 5,    /* a KKT or step-size scalar became NaN/Inf                     */
+    OT_ERR_BUSY = 6        /* server queue full or request over its memory budget          */
+} ot_status;
+
+/* Working precision of the iterates and of the cost stream.  OT_PREC_FP64 is the paper's
+ * own precision (8-byte cost entries, Section 5.1 Table stats).  OT_PREC_FP32 streams X,
+ * the average and C in FP32 while p, q, all row/column sums, KKT pieces, the duality gap
+ * and every control scalar stay in FP64 (the primal step is evaluated in FP64 and rounded
+ * once to FP32). */
+typedef enum { OT_PREC_FP64 = 0, OT_PREC_FP32 = 1 } ot_precision;
+
+/* Cost description (eq. ot; the pixel-grid costs of Section 5.1).
+ *   OT_COST_DENSE            C: m x n FP64, row stride ldc (>= n) elements.
+ *   OT_COST_POINTS_SQEUCLID  C_ij = sum_k (x_ik - y_jk)^2, x: m x dim, y: n x dim FP64.
+ *   OT_COST_POINTS_EUCLID    C_ij = sqrt(sum_k (x_ik - y_jk)^2).
+ *   OT_COST_GRID_SQEUCLID    m = n = side^2 pixels of an side x side image, pixel
+ *                            i = (i / side, i % side); C_ij = scale * squared pixel distance.
+ * For the coordinate kinds `store` = 0 regenerates C_ij inside the iteration kernel from
+ * the coordinates (no cost bytes streamed); `store` = 1 materialises C once in device
+ * memory.  Both produce bit-identical cost values in the working precision. */
+typedef enum {
+    OT_COST_DENSE = 0,
+    OT_COST_POINTS_SQEUCLID = 1,
+    OT_COST_POINTS_EUCLID = 2,
+    OT_COST_GRID_SQEUCLID = 3
+} ot_cost_kind;
+
+typedef struct {
+    int32_t kind;       /* ot_cost_kind                                  */
+    int32_t dim;        /* points kinds: coordinate dimension, 1..3      */
+    int32_t side;       /* grid kind: image side                         */
+    int32_t store;      /* coordinate kinds: 0 regenerate, 1 materialise */
+    int64_t ldc;        /* dense kind: row stride of C in elements       */
+    const double *C;    /* dense kind                                    */
+    const double *x;    /* points kinds: m x dim, row-major              */
+    const double *y;    /* points kinds: n x dim, row-major              */
+    double scale;       /* grid kind: multiplier of the squared distance */
+} ot_cost;
+
+/* One OT instance with its outputs. */
+typedef struct {
+    ot_cost cost;
+    int64_t m, n;        /* m >= 1 sources, n >= 1 targets                           */
+    const double *f;     /* m, >= 0, finite                                          */
+    const double *g;     /* n, >= 0, finite, |sum f - sum g| <= 1e-12 max(sum f, sum g) */
+    double tol;          /* > 0 overrides ot_params.tol for this instance            */
+    void *X_out;         /* nullable; m x n contiguous, FP64 or FP32 per precision   */
+    double *u_out;       /* nullable; m, the row duals p of the returned iterate      */
+    double *v_out;       /* nullable; n, the column duals q                          */
+} ot_problem;
+
+/* Solver parameters.  Defaults (ot_params_default) are the paper's constants:
+ * beta_sufficient 0.1, beta_necessary 0.9, beta_artificial 0.36 (Section 5, adaptive
+ * restart), theta 0.5 and omega0 1 (Section 5, primal weight), tol 1e-4 (Section 5.1).
+ * Readings where the paper is silent:
+ *   kkt_mode 0: relative KKT = sqrt(rel_P^2 + rel_D^2 + rel_G^2) with
+ *     rel_P = ||[X1-f; X^T1-g]|| / ||[f;g]||, rel_D = ||[p1^T+1q^T-C]^+||_F / ||C||_F,
+ *     rel_G = |<C,X> - f^T p - g^T q| / (|<C,X>| + |f^T p + g^T q|);
+ *   kkt_mode 1: denominators 1+||[f;g]||, 1+||C||_F, 1+|<C,X>|+|f^T p+g^T q|.
+ *   eta0 <= 0 selects 1/sqrt(m+n) = 1/||A||_2 (Proposition prop:norm-sharp).
+ *   step_rule 0: accept eta when eta <= omega||dX||^2 + ||dy||^2/omega over
+ *     2|dp^T dX 1 + dq^T dX^T 1| (squared weighted norm), else retry from the same point;
+ *     either way eta <- min((1-(T+1)^-a) eta_bar, (1+(T+1)^-b) eta), a = 0.3, b = 0.6.
+ *   avg_weighting 0: average weighted by the step eta used; 1: uniform (Algorithm 2).
+ *   restart_rule 0: Section 5 adaptive restart to the candidate; 1: Algorithm 2's rule
+ *     KKT(average) <= beta_basic KKT(restart point), restart to the average; 2: never.
+ *   output 0: return the restart candidate that met the tolerance; 1: the current iterate.
+ */
+typedef struct {
+    double tol;
+    int64_t max_iters;        /* accepted iterations                          */
+    int64_t max_passes;       /* step trials (accepted + rejected)            */
+    double time_limit_s;      /* <= 0: none (checked between graph launches)  */
+    int32_t precision;        /* ot_precision                                 */
+    int32_t kkt_mode;
+    int32_t step_rule;        /* 0 adaptive, 1 constant eta                   */
+    int32_t restart_rule;
+    int32_t avg_weighting;
+    int32_t primal_weight_update;  /* 1 on, 0 keep omega0                    */
+    int32_t output;
+    int32_t graph_slots;      /* iteration slots per graph launch, 0 = auto   */
+    double beta_sufficient, beta_necessary, beta_artificial, beta_basic;
+    double theta, omega0, eta0, eps_zero;
+    double step_reduction_exp, step_growth_exp;
+    int32_t tile_vec;         /* columns per lane (1, 2, 4), 0 = autotuned    */
+    int32_t tile_rows;        /* rows per tile (multiple of 4), 0 = autotuned */
+} ot_params;
+
+typedef struct {
+    int32_t status;            /* ot_status of this instance                       */
+    int32_t returned_average;  /* 1 if the returned iterate is the running average */
+    int64_t iterations;        /* accepted PDHG iterations                         */
+    int64_t passes;            /* step trials evaluated (accepted + rejected)      */
+    int64_t restarts;
+    int64_t kernel_passes;     /* streaming passes launched (incl. speculative)    */
+    double objective;          /* <C, X> of the returned X                         */
+    double dual_objective;     /* f^T u + g^T v                                    */
+    double rel_primal, rel_dual, rel_gap, rel_kkt;   /* of the returned triple     */
+    double eta, omega;         /* final step size and primal weight                */
+    double seconds;            /* wall time of the call                            */
+} ot_result;
+
+/* Fill *prm with the defaults described above (precision OT_PREC_FP32). */
+void ot_params_default(ot_params *prm);
+
+/* Device bytes ot_solve needs for this problem when the caller provides the workspace.
+ * Returns 0 and sets ot_last_error() for an invalid problem. */
+size_t ot_workspace_size(const ot_problem *prob, const ot_params *prm);
+
+/* Solve one instance (Algorithm 2 with the Section 5 enhancements) on the current HIP
+ * device.  workspace: nullable device pointer of workspace_bytes >= ot_workspace_size(),
+ * 256-byte aligned.  res: nullable.  Returns the instance status. */
+ot_status ot_solve(const ot_problem *prob, const ot_params *prm, ot_result *res,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Solve `count` independent instances together: every iteration slot is one launch of the
+ * streaming kernel over the tiles of all running instances and one launch of the combine
+ * kernel, so instances of uneven m x n share the GPU.  Each instance follows exactly the
+ * arithmetic of a solo ot_solve with the same parameters and tile shape (results are
+ * bit-identical).  res: array of count results.  Returns OT_OK when every instance
+ * converged, otherwise the first non-OK instance status. */
+ot_status ot_solve_batch(const ot_problem *probs, int32_t count, const ot_params *prm,
+                         ot_result *res, void *stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *ot_last_error(void);
+
+/* Library version string. */
+const char *ot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDOT_H */

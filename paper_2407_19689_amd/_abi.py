@@ -1,0 +1,145 @@
+"""ctypes mirror of ``include/pdot.h``: structures, enums and the library loader.
+
+Argument marshalling only; every step of the solver runs in the HIP library.  Loading
+fails loudly when ``libpdot.so`` has not been built -- there is no fallback path.
+"""
+import ctypes as ct
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdot.so")
+
+# ot_status
+OT_OK = 0
+OT_ERR_INVALID = 1
+OT_ERR_OOM = 2
+OT_ERR_DEVICE = 3
+OT_NOT_CONVERGED = 4
+OT_ERR_NUMERIC = 5
+OT_ERR_BUSY = 6
+STATUS_NAMES = {0: "OK", 1: "ERR_INVALID", 2: "ERR_OOM", 3: "ERR_DEVICE", 4: "NOT_CONVERGED",
+                5: "ERR_NUMERIC", 6: "ERR_BUSY"}
+
+# ot_precision
+OT_PREC_FP64 = 0
+OT_PREC_FP32 = 1
+
+# ot_cost_kind
+OT_COST_DENSE = 0
+OT_COST_POINTS_SQEUCLID = 1
+OT_COST_POINTS_EUCLID = 2
+OT_COST_GRID_SQEUCLID = 3
+
+_D = ct.POINTER(ct.c_double)
+
+
+class OtCost(ct.Structure):
+    _fields_ = [
+        ("kind", ct.c_int32),
+        ("dim", ct.c_int32),
+        ("side", ct.c_int32),
+        ("store", ct.c_int32),
+        ("ldc", ct.c_int64),
+        ("C", ct.c_void_p),
+        ("x", ct.c_void_p),
+        ("y", ct.c_void_p),
+        ("scale", ct.c_double),
+    ]
+
+
+class OtProblem(ct.Structure):
+    _fields_ = [
+        ("cost", OtCost),
+        ("m", ct.c_int64),
+        ("n", ct.c_int64),
+        ("f", ct.c_void_p),
+        ("g", ct.c_void_p),
+        ("tol", ct.c_double),
+        ("X_out", ct.c_void_p),
+        ("u_out", ct.c_void_p),
+        ("v_out", ct.c_void_p),
+    ]
+
+
+class OtParams(ct.Structure):
+    _fields_ = [
+        ("tol", ct.c_double),
+        ("max_iters", ct.c_int64),
+        ("max_passes", ct.c_int64),
+        ("time_limit_s", ct.c_double),
+        ("precision", ct.c_int32),
+        ("kkt_mode", ct.c_int32),
+        ("step_rule", ct.c_int32),
+        ("restart_rule", ct.c_int32),
+        ("avg_weighting", ct.c_int32),
+        ("primal_weight_update", ct.c_int32),
+        ("output", ct.c_int32),
+        ("graph_slots", ct.c_int32),
+        ("beta_sufficient", ct.c_double),
+        ("beta_necessary", ct.c_double),
+        ("beta_artificial", ct.c_double),
+        ("beta_basic", ct.c_double),
+        ("theta", ct.c_double),
+        ("omega0", ct.c_double),
+        ("eta0", ct.c_double),
+        ("eps_zero", ct.c_double),
+        ("step_reduction_exp", ct.c_double),
+        ("step_growth_exp", ct.c_double),
+        ("tile_vec", ct.c_int32),
+        ("tile_rows", ct.c_int32),
+    ]
+
+
+class OtResult(ct.Structure):
+    _fields_ = [
+        ("status", ct.c_int32),
+        ("returned_average", ct.c_int32),
+        ("iterations", ct.c_int64),
+        ("passes", ct.c_int64),
+        ("restarts", ct.c_int64),
+        ("kernel_passes", ct.c_int64),
+        ("objective", ct.c_double),
+        ("dual_objective", ct.c_double),
+        ("rel_primal", ct.c_double),
+        ("rel_dual", ct.c_double),
+        ("rel_gap", ct.c_double),
+        ("rel_kkt", ct.c_double),
+        ("eta", ct.c_double),
+        ("omega", ct.c_double),
+        ("seconds", ct.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# Every symbol the header declares, with (restype, argtypes).
+SIGNATURES = {
+    "ot_params_default": (None, [ct.POINTER(OtParams)]),
+    "ot_workspace_size": (ct.c_size_t, [ct.POINTER(OtProblem), ct.POINTER(OtParams)]),
+    "ot_solve": (ct.c_int, [ct.POINTER(OtProblem), ct.POINTER(OtParams), ct.POINTER(OtResult),
+                            ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "ot_solve_batch": (ct.c_int, [ct.POINTER(OtProblem), ct.c_int32, ct.POINTER(OtParams),
+                                  ct.POINTER(OtResult), ct.c_void_p]),
+    "ot_last_error": (ct.c_char_p, []),
+    "ot_version": (ct.c_char_p, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load ``libpdot.so`` (raises if it is missing: build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2407_19689_amd/build.py "
+                           "(the solver has no CPU fallback)")
+    lib = ct.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,100 @@
+// Internal layout shared by the HIP kernels and the host runtime of the PDHG optimal
+// transport library.  Not part of the public ABI (include/pdot.h is).
+//
+// One iteration "slot" is two launches: the streaming pass kernel over the m x n tiles of
+// every running instance, then the combine kernel over row and column slices, whose last
+// work-group per instance runs the scalar control of Section 5 (restart candidate,
+// restart conditions, step-size check, primal weight, termination) and writes the mode of
+// the next slot into the instance's device-resident control block.  Kernels of a slot
+// whose instance is idle return at once, so a graph of many slots needs no host sync.
+#pragma once
+#include <stdint.h>
+
+namespace pdot {
+
+// What the next pass/combine pair does for an instance.
+enum Mode : int32_t {
+    M_IDLE = 0,     // finished (or never started): both kernels return immediately
+    M_INIT = 1,     // KKT of the start point: ||C||_F and ||[-C]^+||_F, ||[f;g]||
+    M_TRIAL = 2,    // step trial from the current point (first step of an epoch or retry)
+    M_FULL = 3,     // fold the newly accepted iterate into the average, KKT of current and
+                    // average, restart/termination checks, and a speculative trial step
+    M_RESTART = 4,  // distance of the restart point to the previous one (primal weight)
+    M_VERIFY = 5    // exact KKT and objective of the returned triple
+};
+
+enum CostKind : int32_t { C_STORED = 0, C_PTS_SQ = 1, C_PTS_EU = 2, C_GRID_SQ = 3 };
+
+// Roles of the four m x ld plan buffers.  The trial buffer is never the current, the
+// average or the restart anchor, so a role swap replaces every copy.
+enum Role : int32_t { R_CUR = 0, R_TRIAL = 1, R_AVG = 2, R_ANCHOR = 3 };
+
+constexpr int kWG = 256;          // threads per work-group (4 wave64)
+constexpr int kCombEntries = 64;  // rows or columns handled by one combine work-group
+constexpr int kNS = 6;            // per-tile scalars
+constexpr int kNC = 8;            // per-combine-entry scalars
+
+// tile scalar slots
+enum { TS_DX2 = 0, TS_DRES = 1, TS_DRESB = 2, TS_POBJ = 3, TS_POBJB = 4, TS_AUX = 5 };
+// combine scalar slots
+enum { CS_PRES = 0, CS_DOBJ = 1, CS_PRESB = 2, CS_DOBJB = 3, CS_DY2 = 4, CS_INTER = 5,
+       CS_AUX = 6, CS_SPARE = 7 };
+
+struct Prm {
+    double tol;
+    int64_t max_iters, max_passes;
+    int32_t kkt_mode, step_rule, restart_rule, avg_weighting;
+    int32_t pwu, output, pad0, pad1;
+    double beta_suff, beta_nec, beta_art, beta_basic;
+    double theta, eps_zero, red_exp, grow_exp;
+};
+
+// Device-resident control block of one instance (written only by the combine kernel's
+// last work-group, or by the host between graph launches).
+struct Ctl {
+    int32_t mode, status;
+    int32_t xr[4];          // role -> physical plan buffer
+    int32_t pv, pbv, rsv;   // current version of p/q, of the averaged p/q, of the sums
+    int32_t cand_avg;       // last restart candidate is the average
+    int32_t ret_x, ret_avg; // returned plan buffer / returned duals are the averages
+    int32_t stop;           // host request: stop at the next decision point
+    int32_t pad;
+    int64_t T, k, passes, restarts, kpasses;
+    double eta, omega, wsum, a_fold;
+    double K_start, K_prev, K_cand;
+    double norm_b, norm_c;
+    double r_obj, r_dobj, r_relP, r_relD, r_relG, r_kkt;
+};
+
+struct Inst {
+    int64_t m, n, ld;       // ld: row stride (elements) of every m x n buffer
+    int32_t cost, dim, side, vec;
+    int32_t rows, ncb, nrb, ntiles;
+    int32_t ncomb, pad0;
+    double scale;
+    void *X[4];
+    const void *C;          // stored cost in the working precision (C_STORED)
+    const double *xs, *ys;  // coordinates (points kinds)
+    const double *f, *g;
+    double *p[2], *q[2], *pb[2], *qb[2];
+    double *pa, *qa;
+    double *rs[2], *cs[2];
+    double *rsb, *csb;
+    double *rowpart;        // [ncb][2][m]  (value, delta)
+    double *colpart;        // [nrb][2][n]
+    double *tilescal;       // [ntiles][kNS]
+    double *combscal;       // [ncomb][kNC]
+    uint32_t *counter;
+    Ctl *ctl;
+    Prm prm;
+};
+
+struct Tile {
+    int32_t inst, rb, cb, local;
+};
+
+struct CombEntry {
+    int32_t inst, kind, start, local;  // kind 0: rows [start, start+64), 1: columns
+};
+
+}  // namespace pdot
