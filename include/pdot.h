@@ -133,7 +133,10 @@ typedef struct {
     double theta, omega0, eta0, eps_zero;
     double step_reduction_exp, step_growth_exp;
     int32_t tile_vec;         /* columns per lane (1, 2, 4), 0 = autotuned    */
-    int32_t tile_rows;        /* rows per tile (multiple of 4), 0 = autotuned */
+    int32_t tile_rows;        /* rows per tile (multiple of 16), 0 = autotuned */
+    int32_t profile;          /* 1: launch slots one by one (no graph) and time every
+                                 streaming-pass launch with HIP events (ot_result.pass_ms) */
+    int32_t reserved;
 } ot_params;
 
 typedef struct {
@@ -148,6 +151,13 @@ typedef struct {
     double rel_primal, rel_dual, rel_gap, rel_kkt;   /* of the returned triple     */
     double eta, omega;         /* final step size and primal weight                */
     double seconds;            /* wall time of the call                            */
+    int64_t mode_passes[6];    /* streaming passes by kind: 0 unused, 1 start-point KKT,
+                                  2 step trial, 3 average fold + KKT + trial, 4 restart
+                                  distance, 5 final verification                      */
+    double pass_bytes;         /* algorithmic HBM bytes of those passes (plan, average
+                                  and cost streams; partial sums excluded)            */
+    double pass_ms;            /* profile mode: summed duration of the pass launches   */
+    double combine_ms;         /* profile mode: summed duration of the combine launches*/
 } ot_result;
 
 /* Fill *prm with the defaults described above (precision OT_PREC_FP32). */

@@ -7,7 +7,8 @@ import ctypes as ct
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpdot.so")
+# PDOT_LIBRARY selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PDOT_LIBRARY") or os.path.join(HERE, "libpdot.so")
 
 # ot_status
 OT_OK = 0
@@ -87,6 +88,8 @@ class OtParams(ct.Structure):
         ("step_growth_exp", ct.c_double),
         ("tile_vec", ct.c_int32),
         ("tile_rows", ct.c_int32),
+        ("profile", ct.c_int32),
+        ("reserved", ct.c_int32),
     ]
 
 
@@ -107,10 +110,16 @@ class OtResult(ct.Structure):
         ("eta", ct.c_double),
         ("omega", ct.c_double),
         ("seconds", ct.c_double),
+        ("mode_passes", ct.c_int64 * 6),
+        ("pass_bytes", ct.c_double),
+        ("pass_ms", ct.c_double),
+        ("combine_ms", ct.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["mode_passes"] = list(self.mode_passes)
+        return d
 
 
 # Every symbol the header declares, with (restype, argtypes).

@@ -58,9 +58,11 @@ struct Ctl {
     int32_t cand_avg;       // last restart candidate is the average
     int32_t ret_x, ret_avg; // returned plan buffer / returned duals are the averages
     int32_t stop;           // host request: stop at the next decision point
-    int32_t pad;
+    int32_t verify_fails;   // final verifications that did not confirm the tolerance
     int64_t T, k, passes, restarts, kpasses;
+    int64_t mcount[6];      // slots executed per mode (index: Mode)
     double eta, omega, wsum, a_fold;
+    double tol_eff;         // internal termination threshold (tightened on a failed verify)
     double K_start, K_prev, K_cand;
     double norm_b, norm_c;
     double r_obj, r_dobj, r_relP, r_relD, r_relG, r_kkt;
@@ -68,6 +70,7 @@ struct Ctl {
 
 struct Inst {
     int64_t m, n, ld;       // ld: row stride (elements) of every m x n buffer
+    int64_t m_alloc;        // rows allocated for plan/cost buffers: m rounded up to 16
     int32_t cost, dim, side, vec;
     int32_t rows, ncb, nrb, ntiles;
     int32_t ncomb, pad0;
@@ -80,8 +83,8 @@ struct Inst {
     double *pa, *qa;
     double *rs[2], *cs[2];
     double *rsb, *csb;
-    double *rowpart;        // [ncb][2][m]  (value, delta)
-    double *colpart;        // [nrb][2][n]
+    double *rowpart;        // [ncb][m]  row sums of each column band
+    double *colpart;        // [nrb][n]  column sums of each row block
     double *tilescal;       // [ntiles][kNS]
     double *combscal;       // [ncomb][kNC]
     uint32_t *counter;

@@ -25,6 +25,21 @@
 
 #include "pdot_internal.h"
 
+// Rows each wave keeps in flight per loop step, for FP32 and FP64 plans.
+#ifndef PDOT_RU_F32
+#define PDOT_RU_F32 2
+#endif
+#ifndef PDOT_RU_F64
+#define PDOT_RU_F64 2
+#endif
+// Waves per SIMD the streaming kernel is compiled for (bounds its registers).
+#ifndef PDOT_PASS_WAVES
+#define PDOT_PASS_WAVES 2
+#endif
+#ifndef PDOT_NT_STORES
+#define PDOT_NT_STORES 1
+#endif
+
 namespace pdot {
 
 // ------------------------------------------------------------------ small helpers
@@ -38,267 +53,445 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Every buffer lives in device global memory.  Pointers read out of the instance table
+// are generic pointers; qualifying them as global lets the compiler use global (not flat)
+// memory instructions, whose completion counters do not serialise against scalar loads.
+// (The host compilation pass of this file only type-checks kernels; it gets no qualifier.)
+// The instance and tile tables (and, inside the streaming kernel, the control blocks) do
+// not change while a kernel runs; reading them through the constant address space lets
+// the compiler use scalar loads into SGPRs instead of vector loads into VGPRs.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define PDOT_GLOBAL __attribute__((address_space(1)))
+#define PDOT_CONST __attribute__((address_space(4)))
+#else
+#define PDOT_GLOBAL
+#define PDOT_CONST
+#endif
+
+template <typename T>
+__device__ __forceinline__ PDOT_GLOBAL T *gp(T *p)
+{
+    return (PDOT_GLOBAL T *)p;
+}
+
+template <typename T>
+__device__ __forceinline__ const PDOT_CONST T *cp(const T *p)
+{
+    return (const PDOT_CONST T *)p;
+}
+
 template <typename T, int N>
 struct alignas(sizeof(T) * N) Pack {
     T v[N];
 };
 
 template <typename T, int N>
-__device__ __forceinline__ void load_pack(const T *__restrict__ p, T (&o)[N])
+__device__ __forceinline__ void load_pack(const PDOT_GLOBAL T *__restrict__ p, T (&o)[N])
 {
-    const Pack<T, N> t = *reinterpret_cast<const Pack<T, N> *>(p);
+    const Pack<T, N> t = *reinterpret_cast<const PDOT_GLOBAL Pack<T, N> *>(p);
 #pragma unroll
     for (int i = 0; i < N; ++i) o[i] = t.v[i];
 }
 
 template <typename T, int N>
-__device__ __forceinline__ void store_pack(T *__restrict__ p, const T (&o)[N])
+__device__ __forceinline__ void store_pack(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N])
 {
     Pack<T, N> t;
 #pragma unroll
     for (int i = 0; i < N; ++i) t.v[i] = o[i];
-    *reinterpret_cast<Pack<T, N> *>(p) = t;
+    *reinterpret_cast<PDOT_GLOBAL Pack<T, N> *>(p) = t;
 }
 
 // Squared distance of two points, summed over coordinates in index order with every
 // product and sum rounded separately (the same value wherever it is evaluated).
-__device__ __forceinline__ double sqdist(const double *xi, const double *yj, int dim)
+template <typename P1, typename P2>
+__device__ __forceinline__ double sqdist(P1 xi, P2 yj, int dim)
 {
+#pragma clang fp contract(off)
     double t = xi[0] - yj[0];
-    double s = __dmul_rn(t, t);
+    double s = t * t;
     for (int k = 1; k < dim; ++k) {
         t = xi[k] - yj[k];
-        s = __dadd_rn(s, __dmul_rn(t, t));
+        s = s + t * t;
     }
     return s;
 }
 
-// Cost entry in the working precision TX, returned widened to FP64.  Used both by the
-// materialising kernel and inside the pass, so stored and regenerated costs are equal.
+// Costs are evaluated in the working precision TX and widened to FP64; the materialising
+// kernel calls the same functions, so stored and regenerated costs are bit-identical.
 template <typename TX>
 __device__ __forceinline__ double round_to(double v)
 {
     return (double)(TX)v;
 }
 
-__device__ __forceinline__ double grid_cost(int ia, int ib, int ja, int jb, double scale)
+// Grid kind, C_ij = scale * ((a_i - a_j)^2 + (b_i - b_j)^2) for pixels (a, b).  The
+// coordinates are small integers held exactly in floats.  FP64: exact integer distance
+// times scale, one FP64 rounding (the oracle's value).  FP32: the exact integer distance
+// times scale rounded to FP32, one FP32 rounding.
+template <typename TX>
+__device__ __forceinline__ double grid_cost(float ia, float ib, float ja, float jb, double scale,
+                                            float scale32);
+
+template <>
+__device__ __forceinline__ double grid_cost<double>(float ia, float ib, float ja, float jb,
+                                                    double scale, float)
 {
-    const int da = ia - ja, db = ib - jb;
-    return (double)(da * da + db * db) * scale;
+#pragma clang fp contract(off)
+    const double da = (double)ia - (double)ja, db = (double)ib - (double)jb;
+    return (da * da + db * db) * scale;
+}
+
+template <>
+__device__ __forceinline__ double grid_cost<float>(float ia, float ib, float ja, float jb, double,
+                                                   float scale32)
+{
+#pragma clang fp contract(off)
+    const float da = ia - ja, db = ib - jb;
+    const float d2 = da * da + db * db;   // exact: an integer below 2^24
+    return (double)(d2 * scale32);
+}
+
+// 32-bit integer mixer "lowbias32" (C. Wellons, hash-prospector): a bijection on 32-bit
+// words with low avalanche bias.  Used as a counter-based generator for the rounding below.
+__device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// Store of the running average.  FP64 storage keeps the value.  FP32 storage rounds
+// stochastically: for v >= 0 the 29 FP64 mantissa bits that FP32 drops are incremented by
+// 29 random bits and then cleared, so v is stored as its upper FP32 neighbour with
+// probability (v - lo)/(hi - lo) and as the lower one otherwise (exact in the FP32 normal
+// range).  Round-to-nearest would drop every fold increment below half an ulp, a bias that
+// grows linearly with the epoch length; the stochastic store is unbiased.
+template <typename TX>
+__device__ __forceinline__ TX store_avg(double v, uint32_t h);
+
+template <>
+__device__ __forceinline__ double store_avg<double>(double v, uint32_t)
+{
+    return v;
+}
+
+template <>
+__device__ __forceinline__ float store_avg<float>(double v, uint32_t h)
+{
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    b += (uint64_t)(h >> 3);
+    b &= ~(uint64_t)0x1FFFFFFFu;
+    return (float)__longlong_as_double((long long)b);
+}
+
+// Move of a 64-bit value between lanes with a DPP pattern (two 32-bit moves); lanes whose
+// source is outside the pattern, or whose row is masked off, read 0.
+template <int CTRL, int ROW_MASK, bool BOUND_ZERO>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, BOUND_ZERO);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, BOUND_ZERO);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes with DPP moves: a scan inside each row of 16 lanes (shifts 1, 2,
+// 4, 8), then the row totals are carried across rows with the row broadcasts of lanes 15
+// and 31.  The total is in lane 63; the combination order is fixed.
+__device__ __forceinline__ double wave_sum_to63(double v)
+{
+    v += dpp64<0x111, 0xF, true>(v);   // row_shr:1
+    v += dpp64<0x112, 0xF, true>(v);   // row_shr:2
+    v += dpp64<0x114, 0xF, true>(v);   // row_shr:4
+    v += dpp64<0x118, 0xF, true>(v);   // row_shr:8
+    v += dpp64<0x142, 0xA, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp64<0x143, 0xC, false>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
 }
 
 // ------------------------------------------------------------------ streaming pass
 
-template <typename TX, int VEC, int COST, int MODE>
-__device__ void tile_body(const Inst &I, const Ctl &st, const Tile &tl, double *lds)
+// Non-temporal vector store of VEC plan entries (16-byte pieces): the plan and the
+// average are written once per pass and read back only by the next pass.
+template <typename T, int N>
+__device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N])
 {
-    constexpr int RU = 2;                       // rows in flight per wave
+    if constexpr (!PDOT_NT_STORES) {
+        store_pack<T, N>(p, o);
+    } else if constexpr (sizeof(T) * N >= 16) {
+        constexpr int E = 16 / sizeof(T);   // entries per 16-byte piece
+        typedef T V __attribute__((ext_vector_type(E)));
+#pragma unroll
+        for (int c = 0; c < N / E; ++c) {
+            V v;
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = o[c * E + e];
+            __builtin_nontemporal_store(v, reinterpret_cast<PDOT_GLOBAL V *>(p) + c);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e) __builtin_nontemporal_store(o[e], p + e);
+    }
+}
+
+// One tile of the streaming pass.  Rows are processed RU at a time per wave (wave w takes
+// rows i0+w, i0+w+4, ...); the tile's row range is a multiple of 4*RU inside the padded
+// allocation, so every row touched exists in memory.  Padding rows (i >= m) use p_i = -inf
+// and padding columns (j >= n) q_j = -inf: the gradient is then +inf, the projected step
+// is 0 and no residual term is positive, so padding contributes exactly zero without a
+// masked code path.  Plan padding is zero and stays zero.  Per-row quantities (row base,
+// duals, pixel coordinates, hash) are wave-uniform and live in scalar registers.
+template <typename TX, int VEC, int COST, int MODE>
+__device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &tl, double *lds)
+{
+    constexpr int RU = sizeof(TX) == 4 ? PDOT_RU_F32 : PDOT_RU_F64;   // rows in flight per wave
     constexpr bool kX = MODE != M_INIT;         // reads the plan
     constexpr bool kCost = MODE != M_RESTART;   // needs C
     constexpr bool kTrial = MODE == M_TRIAL || MODE == M_FULL;
     constexpr bool kFold = MODE == M_FULL;
     constexpr bool kRowCol = kTrial || MODE == M_VERIFY;
-    constexpr bool kDres = MODE == M_FULL || MODE == M_VERIFY || MODE == M_INIT;
+    constexpr bool kGrid = COST == C_GRID_SQ;
+    constexpr bool kPts = COST == C_PTS_SQ || COST == C_PTS_EU;
+    constexpr double kNegInf = -__builtin_huge_val();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    // wave index as a wave-uniform value, so row indices and per-row data stay scalar
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t m = I.m, n = I.n, ld = I.ld;
     const int64_t i0 = (int64_t)tl.rb * I.rows;
-    const int64_t i1 = min(m, i0 + (int64_t)I.rows);
-    const int64_t j0 = (int64_t)tl.cb * (64 * VEC) + (int64_t)lane * VEC;
-    const bool active = j0 < n;
-    const bool full = j0 + VEC <= n;
+    const int64_t ie = min(I.m_alloc, i0 + (int64_t)I.rows);
+    const int64_t jband = (int64_t)tl.cb * (64 * VEC);   // first column of the tile (uniform)
+    const uint32_t jl = (uint32_t)lane * VEC;            // lane's first column in the tile
+    const int64_t j0 = jband + jl;
+    const bool active = j0 < n;   // lanes wholly beyond n touch no memory
 
     const int xc = (MODE == M_VERIFY) ? st.ret_x : st.xr[R_CUR];
-    const TX *__restrict__ Xc = (const TX *)I.X[xc];
-    TX *__restrict__ Xt = (TX *)I.X[st.xr[R_TRIAL]];
-    TX *__restrict__ Xb = (TX *)I.X[st.xr[R_AVG]];
-    const TX *__restrict__ Xa = (const TX *)I.X[st.xr[R_ANCHOR]];
-    const TX *__restrict__ Cs = (const TX *)I.C;
+    const PDOT_GLOBAL TX *__restrict__ Xc = gp((const TX *)I.X[xc]);
+    PDOT_GLOBAL TX *__restrict__ Xt = gp((TX *)I.X[st.xr[R_TRIAL]]);
+    PDOT_GLOBAL TX *__restrict__ Xb = gp((TX *)I.X[st.xr[R_AVG]]);
+    const PDOT_GLOBAL TX *__restrict__ Xa = gp((const TX *)I.X[st.xr[R_ANCHOR]]);
+    const PDOT_GLOBAL TX *__restrict__ Cs = gp((const TX *)I.C);
     const bool use_avg_duals = (MODE == M_VERIFY) && st.ret_avg;
-    const double *__restrict__ pc = use_avg_duals ? I.pb[st.pbv] : I.p[st.pv];
-    const double *__restrict__ qc = use_avg_duals ? I.qb[st.pbv] : I.q[st.pv];
-    const double *__restrict__ pbc = I.pb[st.pbv];
-    const double *__restrict__ qbc = I.qb[st.pbv];
+    const PDOT_GLOBAL double *__restrict__ pc = gp(use_avg_duals ? I.pb[st.pbv] : I.p[st.pv]);
+    const PDOT_GLOBAL double *__restrict__ qc = gp(use_avg_duals ? I.qb[st.pbv] : I.q[st.pv]);
+    const PDOT_GLOBAL double *__restrict__ pbc = gp(I.pb[st.pbv]);
+    const PDOT_GLOBAL double *__restrict__ qbc = gp(I.qb[st.pbv]);
+    const PDOT_GLOBAL double *__restrict__ xs = gp(I.xs);
+    const PDOT_GLOBAL double *__restrict__ ys = gp(I.ys);
+    PDOT_GLOBAL double *__restrict__ rowpart = gp(I.rowpart);
+    PDOT_GLOBAL double *__restrict__ colpart = gp(I.colpart);
     const double tau = st.eta / st.omega;
     const double a = st.a_fold;
     const bool first_fold = st.k == 1;
+    const uint32_t hiter = mix32((uint32_t)st.T * 0x85EBCA77U + 0x27D4EB2FU);
     const double scale = I.scale;
+    const float scale32 = (float)I.scale;
     const int dim = I.dim, side = I.side;
 
     // per-lane column context
+    uint32_t hcol[VEC];
     double qv[VEC], qbv[VEC];
-    int gja[VEC], gjb[VEC];
+    bool colok[VEC];
+    float gja[VEC], gjb[VEC];
     double yc[VEC][3];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int64_t j = j0 + v;
         const bool ok = j < n;
-        qv[v] = (ok && kDres) || (ok && kTrial) ? qc[j] : 0.0;
-        qbv[v] = (ok && kFold) ? qbc[j] : 0.0;
-        gja[v] = 0;
-        gjb[v] = 0;
+        const int64_t jc = ok ? j : n - 1;
+        colok[v] = ok;
+        hcol[v] = mix32((uint32_t)j * 0x9E3779B9U + 0x632BE5ABU);
+        qv[v] = ok ? qc[jc] : kNegInf;
+        qbv[v] = (ok && kFold) ? qbc[jc] : kNegInf;
+        gja[v] = gjb[v] = 0.0f;
         yc[v][0] = yc[v][1] = yc[v][2] = 0.0;
-        if constexpr (COST == C_GRID_SQ) {
-            if (ok) {
-                gja[v] = (int)(j / side);
-                gjb[v] = (int)(j % side);
-            }
+        if constexpr (kGrid) {
+            gja[v] = (float)(int)((uint32_t)jc / (uint32_t)side);
+            gjb[v] = (float)(int)((uint32_t)jc % (uint32_t)side);
         }
-        if constexpr (COST == C_PTS_SQ || COST == C_PTS_EU) {
-            if (ok)
-                for (int k = 0; k < dim; ++k) yc[v][k] = I.ys[j * dim + k];
+        if constexpr (kPts) {
+            for (int k = 0; k < dim; ++k) yc[v][k] = ys[jc * dim + k];
         }
     }
 
-    double csv[VEC], csd[VEC];
+    double csv[VEC];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) csv[v] = csd[v] = 0.0;
+    for (int v = 0; v < VEC; ++v) csv[v] = 0.0;
     double s_dx2 = 0.0, s_dres = 0.0, s_dresb = 0.0, s_pobj = 0.0, s_pobjb = 0.0, s_aux = 0.0;
 
-    for (int64_t ib = i0 + wave; ib < i1; ib += 4 * RU) {
-        TX xr[RU][VEC], cr[RU][VEC], br[RU][VEC], ar[RU][VEC];
+    // pixel coordinates of this wave's next row to load, advanced by 4 rows at a time
+    int ga = 0, gb = 0;
+    if constexpr (kGrid) {
+        const uint32_t r0 = (uint32_t)(i0 + wave);
+        ga = (int)(r0 / (uint32_t)side);
+        gb = (int)(r0 % (uint32_t)side);
+    }
+
+    // Registers of RU rows: the plan entries and the wave-uniform row data.
+    struct Rows {
+        TX x[RU][VEC], c[RU][VEC], b[RU][VEC], an[RU][VEC];
         double pi[RU], pbi[RU];
         double xi[RU][3];
-        int gia[RU], gib[RU];
-        bool rv_ok[RU];
+        float gia[RU], gib[RU];
+    };
+
+    auto load_rows = [&](int64_t ib, Rows &R) {
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
             const int64_t i = ib + 4 * u;
-            rv_ok[u] = i < i1;
-            const int64_t ii = rv_ok[u] ? i : ib;      // clamp: loads stay in bounds
-            const int64_t off = ii * ld + j0;
-            pi[u] = (kTrial || kDres) ? pc[ii] : 0.0;
-            pbi[u] = kFold ? pbc[ii] : 0.0;
-            gia[u] = gib[u] = 0;
-            xi[u][0] = xi[u][1] = xi[u][2] = 0.0;
-            if constexpr (COST == C_GRID_SQ) {
-                gia[u] = (int)(ii / side);
-                gib[u] = (int)(ii % side);
+            const bool rok = i < m;
+            const int64_t ic = rok ? i : m - 1;
+            const int64_t rowoff = i * ld + jband;   // uniform row base; lanes add jl
+            R.pi[u] = rok ? pc[i] : kNegInf;
+            R.pbi[u] = (rok && kFold) ? pbc[i] : kNegInf;
+            R.gia[u] = (float)ga;
+            R.gib[u] = (float)gb;
+            if constexpr (kGrid) {
+                gb += 4;
+                while (gb >= side) {
+                    gb -= side;
+                    ga += 1;
+                }
             }
-            if constexpr (COST == C_PTS_SQ || COST == C_PTS_EU) {
-                for (int k = 0; k < dim; ++k) xi[u][k] = I.xs[ii * dim + k];
+            R.xi[u][0] = R.xi[u][1] = R.xi[u][2] = 0.0;
+            if constexpr (kPts) {
+                for (int k = 0; k < dim; ++k) R.xi[u][k] = xs[ic * dim + k];
             }
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) xr[u][v] = cr[u][v] = br[u][v] = ar[u][v] = (TX)0;
+            for (int v = 0; v < VEC; ++v) R.x[u][v] = R.c[u][v] = R.b[u][v] = R.an[u][v] = (TX)0;
             if (active) {
-                if constexpr (kX) load_pack<TX, VEC>(Xc + off, xr[u]);
-                if constexpr (kCost && COST == C_STORED) load_pack<TX, VEC>(Cs + off, cr[u]);
-                if constexpr (kFold) load_pack<TX, VEC>(Xb + off, br[u]);
-                if constexpr (MODE == M_RESTART) load_pack<TX, VEC>(Xa + off, ar[u]);
+                if constexpr (kX) load_pack<TX, VEC>(Xc + rowoff + jl, R.x[u]);
+                if constexpr (kCost && COST == C_STORED) load_pack<TX, VEC>(Cs + rowoff + jl, R.c[u]);
+                if constexpr (kFold) load_pack<TX, VEC>(Xb + rowoff + jl, R.b[u]);
+                if constexpr (MODE == M_RESTART) load_pack<TX, VEC>(Xa + rowoff + jl, R.an[u]);
             }
         }
+    };
 
-        double rsum[RU], rdel[RU];
+    auto compute_rows = [&](int64_t ib, const Rows &R) {
+        double rsum[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
-            rsum[u] = rdel[u] = 0.0;
-            if (!active || !rv_ok[u]) continue;
-            const int64_t off = (ib + 4 * u) * ld + j0;
+            rsum[u] = 0.0;
+            const int64_t i = ib + 4 * u;
+            const uint32_t hrow = mix32((uint32_t)i ^ hiter);
             TX xn_out[VEC], xb_out[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                const bool ok = full || (j0 + v < n);
-                const double xd = (double)xr[u][v];
+                const double xd = (double)R.x[u][v];
                 double cd = 0.0;
                 if constexpr (kCost) {
                     if constexpr (COST == C_STORED) {
-                        cd = (double)cr[u][v];
-                    } else if constexpr (COST == C_GRID_SQ) {
-                        cd = round_to<TX>(grid_cost(gia[u], gib[u], gja[v], gjb[v], scale));
+                        cd = (double)R.c[u][v];
+                    } else if constexpr (kGrid) {
+                        cd = grid_cost<TX>(R.gia[u], R.gib[u], gja[v], gjb[v], scale, scale32);
                     } else {
-                        double s2 = sqdist(xi[u], yc[v], dim);
+                        double s2 = sqdist(R.xi[u], yc[v], dim);
                         if constexpr (COST == C_PTS_EU) s2 = sqrt(s2);
                         cd = round_to<TX>(s2);
                     }
                 }
                 xn_out[v] = (TX)0;
                 xb_out[v] = (TX)0;
-                if (!ok) continue;
                 if constexpr (MODE == M_INIT) {
-                    s_aux += cd * cd;
-                    const double nd = (pi[u] + qv[v]) - cd;
-                    s_dres += nd > 0.0 ? nd * nd : 0.0;
+                    const double cm = (colok[v] && i < m) ? cd : 0.0;
+                    s_aux += cm * cm;
+                    const double nd = fmax((R.pi[u] + qv[v]) - cd, 0.0);
+                    s_dres += nd * nd;
                 }
                 if constexpr (MODE == M_RESTART) {
-                    const double d = xd - (double)ar[u][v];
+                    const double d = xd - (double)R.an[u][v];
                     s_aux += d * d;
                 }
                 if constexpr (MODE == M_VERIFY) {
-                    const double nd = (pi[u] + qv[v]) - cd;
-                    s_dres += nd > 0.0 ? nd * nd : 0.0;
+                    const double nd = fmax((R.pi[u] + qv[v]) - cd, 0.0);
+                    s_dres += nd * nd;
                     s_pobj += cd * xd;
                     rsum[u] += xd;
                     csv[v] += xd;
                 }
                 if constexpr (kTrial) {
-                    const double s = pi[u] + qv[v];
-                    const double gr = cd - s;                 // G_ij = C_ij - p_i - q_j
+                    const double sg = R.pi[u] + qv[v];
+                    const double gr = cd - sg;                // G_ij = C_ij - p_i - q_j
                     if constexpr (kFold) {
                         // KKT pieces of the current iterate (its duals are p, q)
-                        s_dres += gr < 0.0 ? gr * gr : 0.0;
+                        const double ng = fmin(gr, 0.0);
+                        s_dres += ng * ng;
                         s_pobj += cd * xd;
-                        // fold the current iterate into the running average
-                        const double xbn = first_fold ? xd : (1.0 - a) * (double)br[u][v] + a * xd;
-                        const TX xbt = (TX)xbn;
-                        xb_out[v] = xbt;
-                        const double nb = (pbi[u] + qbv[v]) - cd;
-                        s_dresb += nb > 0.0 ? nb * nb : 0.0;
-                        s_pobjb += cd * (double)xbt;
+                        // fold the current iterate into the running average; the averaged
+                        // objective uses the value before storage rounding, like the
+                        // averaged row and column sums
+                        const double xbd = (double)R.b[u][v];
+                        const double xbn = first_fold ? xd : (1.0 - a) * xbd + a * xd;
+                        xb_out[v] = store_avg<TX>(xbn, hrow ^ hcol[v]);
+                        const double nb = fmax((R.pbi[u] + qbv[v]) - cd, 0.0);
+                        s_dresb += nb * nb;
+                        s_pobjb += cd * xbn;
                     }
                     const double y = xd - tau * gr;
-                    const TX xn = (TX)(y > 0.0 ? y : 0.0);
+                    const TX xn = (TX)fmax(y, 0.0);
                     xn_out[v] = xn;
                     const double xnd = (double)xn;
                     const double d = xnd - xd;
                     rsum[u] += xnd;
-                    rdel[u] += d;
                     csv[v] += xnd;
-                    csd[v] += d;
                     s_dx2 += d * d;
                 }
             }
-            if constexpr (kTrial) store_pack<TX, VEC>(Xt + off, xn_out);
-            if constexpr (kFold) store_pack<TX, VEC>(Xb + off, xb_out);
+            if (active) {
+                const int64_t rowoff = i * ld + jband;
+                if constexpr (kTrial) store_pack_nt<TX, VEC>(Xt + rowoff + jl, xn_out);
+                if constexpr (kFold) store_pack_nt<TX, VEC>(Xb + rowoff + jl, xb_out);
+            }
+            // keep one row's arithmetic together: bounds the live temporaries
+            __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (kRowCol) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
-                const double s = wave_sum(rsum[u]);
-                double d = 0.0;
-                if constexpr (kTrial) d = wave_sum(rdel[u]);
-                if (lane == 0 && rv_ok[u]) {
-                    const int64_t i = ib + 4 * u;
-                    I.rowpart[(int64_t)(2 * tl.cb) * m + i] = s;
-                    if constexpr (kTrial) I.rowpart[(int64_t)(2 * tl.cb + 1) * m + i] = d;
-                }
+                const double sr = wave_sum_to63(rsum[u]);
+                const int64_t i = ib + 4 * u;
+                if (lane == 63 && i < m) rowpart[(int64_t)tl.cb * m + i] = sr;
             }
         }
+    };
+
+    // Software pipeline: the loads of the next RU rows are issued before the arithmetic
+    // of the current ones, alternating between two register sets.
+    const int64_t step = 4 * RU;
+    Rows A, B;
+    int64_t ib = i0 + wave;
+    if (ib < ie) load_rows(ib, A);
+    while (ib < ie) {
+        if (ib + step < ie) load_rows(ib + step, B);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_rows(ib, A);
+        ib += step;
+        if (ib >= ie) break;
+        if (ib + step < ie) load_rows(ib + step, A);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_rows(ib, B);
+        ib += step;
     }
 
     // column partials: combine the four waves in a fixed order
     if constexpr (kRowCol) {
-        double *cl = lds;   // [3][2*VEC][64]
+        double *cl = lds;   // [3][VEC][64]
         if (wave > 0) {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                cl[((wave - 1) * 2 * VEC + 2 * v) * 64 + lane] = csv[v];
-                cl[((wave - 1) * 2 * VEC + 2 * v + 1) * 64 + lane] = csd[v];
-            }
+            for (int v = 0; v < VEC; ++v) cl[((wave - 1) * VEC + v) * 64 + lane] = csv[v];
         }
         __syncthreads();
         if (wave == 0 && active) {
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                double sv = csv[v], sd = csd[v];
-                for (int w = 0; w < 3; ++w) {
-                    sv += cl[(w * 2 * VEC + 2 * v) * 64 + lane];
-                    sd += cl[(w * 2 * VEC + 2 * v + 1) * 64 + lane];
-                }
+                double sv = csv[v];
+                for (int w = 0; w < 3; ++w) sv += cl[(w * VEC + v) * 64 + lane];
                 const int64_t j = j0 + v;
-                if (j < n) {
-                    I.colpart[(int64_t)(2 * tl.rb) * n + j] = sv;
-                    if constexpr (kTrial) I.colpart[(int64_t)(2 * tl.rb + 1) * n + j] = sd;
-                }
+                if (j < n) colpart[(int64_t)tl.rb * n + j] = sv;
             }
         }
         __syncthreads();
@@ -310,12 +503,12 @@ __device__ void tile_body(const Inst &I, const Ctl &st, const Tile &tl, double *
         double vals[kNS] = {s_dx2, s_dres, s_dresb, s_pobj, s_pobjb, s_aux};
 #pragma unroll
         for (int s = 0; s < kNS; ++s) {
-            const double r = wave_sum(vals[s]);
-            if (lane == 0) sl[wave * kNS + s] = r;
+            const double r = wave_sum_to63(vals[s]);
+            if (lane == 63) sl[wave * kNS + s] = r;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double *dst = I.tilescal + (int64_t)tl.local * kNS;
+            PDOT_GLOBAL double *dst = gp(I.tilescal) + (int64_t)tl.local * kNS;
             for (int s = 0; s < kNS; ++s)
                 dst[s] = ((sl[s] + sl[kNS + s]) + sl[2 * kNS + s]) + sl[3 * kNS + s];
         }
@@ -324,14 +517,15 @@ __device__ void tile_body(const Inst &I, const Ctl &st, const Tile &tl, double *
 }
 
 template <typename TX, int VEC, int COST>
-__global__ __launch_bounds__(kWG) void k_pass(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PDOT_PASS_WAVES)))
+void k_pass(const Inst *__restrict__ insts,
                                               const Tile *__restrict__ tiles, int ntiles)
 {
     __shared__ double lds[3 * 2 * 4 * 64 + 4 * kNS];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile tl = tiles[t];
-        const Inst &I = insts[tl.inst];
-        const Ctl st = *I.ctl;
+        const Tile tl = cp(tiles)[t];
+        const PDOT_CONST Inst &I = cp(insts)[tl.inst];
+        const Ctl st = *cp((const Ctl *)I.ctl);
         switch (st.mode) {
         case M_INIT: tile_body<TX, VEC, COST, M_INIT>(I, st, tl, lds); break;
         case M_TRIAL: tile_body<TX, VEC, COST, M_TRIAL>(I, st, tl, lds); break;
@@ -434,6 +628,7 @@ __device__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double
 __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const double *ts)
 {
     c.kpasses += 1;
+    c.mcount[mode] += 1;
     if (mode == M_INIT) {
         c.norm_b = sqrt(cs[CS_AUX]);
         c.norm_c = sqrt(ts[TS_AUX]);
@@ -443,7 +638,7 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
         if (!(K == K) || !(c.norm_c < INFINITY)) {
             c.status = ST_NUMERIC;
             c.mode = M_IDLE;
-        } else if (K <= P.tol) {
+        } else if (K <= c.tol_eff) {
             finish(c, P, ST_OK);
         } else if (limits_hit(c, P)) {
             finish(c, P, ST_NOT_CONVERGED);
@@ -470,7 +665,7 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
             return;
         }
         c.K_cand = K;
-        if (K <= P.tol) {
+        if (K <= c.tol_eff) {
             finish(c, P, ST_OK);
             return;
         }
@@ -533,7 +728,19 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
         c.r_relD = rel[1];
         c.r_relG = rel[2];
         c.r_kkt = K;
-        if (c.status == ST_OK && !(K == K)) c.status = ST_NUMERIC;
+        if (c.status == ST_OK && !(K == K)) {
+            c.status = ST_NUMERIC;
+        } else if (c.status == ST_OK && K > P.tol && c.verify_fails < 8) {
+            // The running estimate met the tolerance but the returned arrays do not (FP32
+            // storage of the average); tighten the internal threshold and keep iterating
+            // from the unchanged state.
+            c.verify_fails += 1;
+            const double ratio = P.tol / K;
+            c.tol_eff = c.tol_eff * (ratio < 0.9 ? ratio : 0.9);
+            c.status = ST_RUNNING;
+            c.mode = M_TRIAL;
+            return;
+        }
         c.mode = M_IDLE;
         return;
     }
@@ -555,19 +762,19 @@ __device__ __forceinline__ double block_sum(double v, double *sl)
 __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                                                  const CombEntry *__restrict__ ents, int nents)
 {
-    __shared__ double part[4][2][64];
+    __shared__ double part[4][64];
     __shared__ double sl[8];
     __shared__ double fin[kNC + kNS];
     __shared__ int is_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     for (int e = blockIdx.x; e < nents; e += gridDim.x) {
-        const CombEntry E = ents[e];
-        const Inst &I = insts[E.inst];
-        const Ctl st = *I.ctl;
+        const CombEntry E = cp(ents)[e];
+        const PDOT_CONST Inst &I = cp(insts)[E.inst];
+        const Ctl st = *gp(I.ctl);
         const int mode = st.mode;
         if (mode == M_IDLE) continue;
-        const Prm &P = I.prm;
+        const Prm P = I.prm;
 
         const bool rows = E.kind == 0;
         const int64_t len = rows ? I.m : I.n;
@@ -575,24 +782,29 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         const bool valid = idx < len;
 
         // phase 1: add the per-tile partial sums of this slice in a fixed order
-        double sv = 0.0, sd = 0.0;
+        double sv = 0.0;
         if (mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY) {
             const int P4 = rows ? I.ncb : I.nrb;
-            const double *src = rows ? I.rowpart : I.colpart;
-            const int pb = (wave * P4) / 4, pe = ((wave + 1) * P4) / 4;
+            const PDOT_GLOBAL double *src = gp(rows ? I.rowpart : I.colpart);
             if (valid) {
-                for (int pp = pb; pp < pe; ++pp) {
-                    sv += src[(int64_t)(2 * pp) * len + idx];
-                    if (mode != M_VERIFY) sd += src[(int64_t)(2 * pp + 1) * len + idx];
+                // wave w adds partials w, w+4, w+8, ...; four independent accumulators keep
+                // several loads in flight; the combination order is fixed
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int pp = wave;
+                for (; pp + 12 < P4; pp += 16) {
+                    const PDOT_GLOBAL double *s0 = src + (int64_t)pp * len + idx;
+                    const int64_t st4 = (int64_t)4 * len;   // 4 partials apart
+                    a0 += s0[0];
+                    a1 += s0[st4];
+                    a2 += s0[2 * st4];
+                    a3 += s0[3 * st4];
                 }
+                for (; pp < P4; pp += 4) a0 += src[(int64_t)pp * len + idx];
+                sv = (a0 + a1) + (a2 + a3);
             }
-            part[wave][0][lane] = sv;
-            part[wave][1][lane] = sd;
+            part[wave][lane] = sv;
             __syncthreads();
-            if (wave == 0) {
-                sv = ((part[0][0][lane] + part[1][0][lane]) + part[2][0][lane]) + part[3][0][lane];
-                sd = ((part[0][1][lane] + part[1][1][lane]) + part[2][1][lane]) + part[3][1][lane];
-            }
+            if (wave == 0) sv = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
             __syncthreads();
         }
 
@@ -602,20 +814,21 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 #pragma unroll
             for (int s = 0; s < kNC; ++s) acc[s] = 0.0;
             if (valid) {
-                const double fi = rows ? I.f[idx] : I.g[idx];
-                double *const *pv2 = rows ? I.p : I.q;
-                double *const *pb2 = rows ? I.pb : I.qb;
-                double *const *rs2 = rows ? I.rs : I.cs;
-                double *sbar = rows ? I.rsb : I.csb;
-                double *anc = rows ? I.pa : I.qa;
-                double *pcur = pv2[st.pv];
-                double *pbcur = pb2[st.pbv];
+                const double fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
+                PDOT_GLOBAL double *pcur = gp(rows ? I.p[st.pv] : I.q[st.pv]);
+                PDOT_GLOBAL double *pnext = gp(rows ? I.p[st.pv ^ 1] : I.q[st.pv ^ 1]);
+                PDOT_GLOBAL double *pbcur = gp(rows ? I.pb[st.pbv] : I.qb[st.pbv]);
+                PDOT_GLOBAL double *pbnext = gp(rows ? I.pb[st.pbv ^ 1] : I.qb[st.pbv ^ 1]);
+                PDOT_GLOBAL double *rscur = gp(rows ? I.rs[st.rsv] : I.cs[st.rsv]);
+                PDOT_GLOBAL double *rsnext = gp(rows ? I.rs[st.rsv ^ 1] : I.cs[st.rsv ^ 1]);
+                PDOT_GLOBAL double *sbar = gp(rows ? I.rsb : I.csb);
+                PDOT_GLOBAL double *anc = gp(rows ? I.pa : I.qa);
                 if (mode == M_INIT) {
                     acc[CS_AUX] = fi * fi;
                 } else if (mode == M_TRIAL || mode == M_FULL) {
                     if (mode == M_FULL) {
                         // KKT of the current iterate: its sums were kept when it was accepted
-                        const double rc = rs2[st.rsv][idx];
+                        const double rc = rscur[idx];
                         double dl = rc - fi;
                         acc[CS_PRES] = dl * dl;
                         acc[CS_DOBJ] = fi * pcur[idx];
@@ -626,62 +839,72 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                         acc[CS_PRESB] = dl * dl;
                         acc[CS_DOBJB] = fi * pbcur[idx];
                     }
-                    // dual step with the extrapolated sums (2X+ - X) = X+ + (X+ - X)
+                    // dual step with the extrapolated sums: (2X+ - X) 1 = 2 X+ 1 - X 1, where
+                    // X 1 (the current iterate's sums) was kept when X was accepted; the
+                    // trial's change of the sums is X+ 1 - X 1
                     const double sigma = st.eta * st.omega;
+                    const double rcur = rscur[idx];
+                    const double sd = sv - rcur;
                     const double er = sv + sd;
                     const double pold = pcur[idx];
                     const double pn = pold + sigma * (fi - er);
                     const double d = pn - pold;
-                    pv2[st.pv ^ 1][idx] = pn;
-                    rs2[st.rsv ^ 1][idx] = sv;
+                    pnext[idx] = pn;
+                    rsnext[idx] = sv;
                     acc[CS_DY2] = d * d;
                     acc[CS_INTER] = d * sd;
                     // tentative running average of the duals for the trial
                     const double w = P.avg_weighting == 1 ? 1.0 : st.eta;
                     const double a2 = w / (st.wsum + w);
-                    pb2[st.pbv ^ 1][idx] = (st.k == 0) ? pn : (1.0 - a2) * pbcur[idx] + a2 * pn;
+                    pbnext[idx] = (st.k == 0) ? pn : (1.0 - a2) * pbcur[idx] + a2 * pn;
                 } else if (mode == M_RESTART) {
                     const double pnew = st.cand_avg ? pbcur[idx] : pcur[idx];
                     const double dd = pnew - anc[idx];
                     acc[CS_AUX] = dd * dd;
                     pcur[idx] = pnew;
                     anc[idx] = pnew;
-                    if (st.cand_avg) rs2[st.rsv][idx] = sbar[idx];
+                    if (st.cand_avg) rscur[idx] = sbar[idx];
                 } else if (mode == M_VERIFY) {
-                    const double *pret = st.ret_avg ? pbcur : pcur;
+                    const PDOT_GLOBAL double *pret = st.ret_avg ? pbcur : pcur;
                     const double dl = sv - fi;
                     acc[CS_PRES] = dl * dl;
                     acc[CS_DOBJ] = fi * pret[idx];
                 }
             }
+            // The entry scalars are handed to the last work-group with agent-scope atomic
+            // stores and loads, which are coherent across the chiplets' L2 caches on their
+            // own; no full-cache write-back or invalidation is needed for them.
 #pragma unroll
             for (int s = 0; s < kNC; ++s) {
                 const double r = wave_sum(acc[s]);
-                if (lane == 0) I.combscal[(int64_t)E.local * kNC + s] = r;
+                if (lane == 0)
+                    __hip_atomic_store(gp(I.combscal) + (int64_t)E.local * kNC + s, r, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
         }
 
         // phase 3: the last work-group of this instance runs the control
-        __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned prev = atomicAdd(I.counter, 1u);
+            // the scalar stores above (same thread) complete before the counter moves
+            __builtin_amdgcn_s_waitcnt(0);
+            const unsigned prev = __hip_atomic_fetch_add(gp(I.counter), 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
             is_last = (prev == (unsigned)(I.ncomb - 1)) ? 1 : 0;
         }
         __syncthreads();
         if (!is_last) continue;
-        __threadfence();
 
         double loc[kNC + kNS];
 #pragma unroll
         for (int s = 0; s < kNC + kNS; ++s) loc[s] = 0.0;
         for (int c = threadIdx.x; c < I.ncomb; c += kWG) {
-            const double *src = I.combscal + (int64_t)c * kNC;
+            const PDOT_GLOBAL double *src = gp(I.combscal) + (int64_t)c * kNC;
 #pragma unroll
             for (int s = 0; s < kNC; ++s) loc[s] += __hip_atomic_load(src + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         for (int t = threadIdx.x; t < I.ntiles; t += kWG) {
-            const double *src = I.tilescal + (int64_t)t * kNS;
+            const PDOT_GLOBAL double *src = gp(I.tilescal) + (int64_t)t * kNS;
 #pragma unroll
             for (int s = 0; s < kNS; ++s) loc[kNC + s] += src[s];
         }
@@ -691,10 +914,10 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            Ctl c = *I.ctl;
+            Ctl c = *gp(I.ctl);
             control(c, P, mode, fin, fin + kNC);
-            *I.ctl = c;
-            __hip_atomic_store(I.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *gp(I.ctl) = c;
+            __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
     }
@@ -720,7 +943,8 @@ __global__ __launch_bounds__(kWG) void k_materialize(TX *__restrict__ dst, int64
             if (kind == C_STORED) {
                 v = src[i * ldc + j];
             } else if (kind == C_GRID_SQ) {
-                v = grid_cost((int)(i / side), (int)(i % side), (int)(j / side), (int)(j % side), scale);
+                v = grid_cost<TX>((float)(int)(i / side), (float)(int)(i % side), (float)(int)(j / side),
+                                  (float)(int)(j % side), scale, (float)scale);
             } else {
                 v = sqdist(xs + i * dim, ys + j * dim, dim);
                 if (kind == C_PTS_EU) v = sqrt(v);

@@ -57,7 +57,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Per-instance layout inside the workspace.
 struct Layout {
-    int64_t m = 0, n = 0, ld = 0;
+    int64_t m = 0, n = 0, ld = 0, m_alloc = 0;
     int fp32 = 1, vec = 4, rows = 64, ncb = 0, nrb = 0, ntiles = 0, ncomb = 0;
     int cost = C_STORED, dim = 0, side = 0;
     bool stored = true;
@@ -84,11 +84,11 @@ int default_vec(int64_t n)
 
 int default_rows(int64_t m, int ncb)
 {
-    // aim for about a thousand tiles on large instances while keeping the column
+    // aim for about four tiles per compute unit on large instances while keeping the column
     // partials (one row of n values per row block) small against the plan
     int64_t r = (m * ncb + 1023) / 1024;
-    r = std::max<int64_t>(8, std::min<int64_t>(256, r));
-    r = (r + 3) / 4 * 4;
+    r = std::max<int64_t>(16, std::min<int64_t>(256, r));
+    r = (r + 15) / 16 * 16;
     return (int)r;
 }
 
@@ -105,6 +105,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
         return fail(OT_ERR_INVALID, "unknown precision");
     L.es = L.fp32 ? 4 : 8;
     L.ld = (pb.n + 63) / 64 * 64;
+    L.m_alloc = (pb.m + 15) / 16 * 16;
     const ot_cost &c = pb.cost;
     switch (c.kind) {
     case OT_COST_DENSE:
@@ -136,7 +137,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     if (L.vec != 1 && L.vec != 2 && L.vec != 4) return fail(OT_ERR_INVALID, "tile_vec must be 1, 2 or 4");
     L.ncb = (int)((pb.n + 64 * L.vec - 1) / (64 * L.vec));
     L.rows = prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb);
-    if (L.rows < 4 || L.rows % 4) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 4");
+    if (L.rows < 16 || L.rows % 16) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 16");
     L.nrb = (int)((pb.m + L.rows - 1) / L.rows);
     const int64_t nt = (int64_t)L.ncb * L.nrb;
     if (nt > (1 << 30)) return fail(OT_ERR_INVALID, "too many tiles");
@@ -149,7 +150,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
         off = align_up(off + bytes);
         return o;
     };
-    const size_t mat = (size_t)L.m * (size_t)L.ld * L.es;
+    const size_t mat = (size_t)L.m_alloc * (size_t)L.ld * L.es;
     for (int b = 0; b < 4; ++b) L.off_X[b] = take(mat);
     L.off_C = L.stored ? take(mat) : 0;
     L.off_xs = L.dim ? take(sizeof(double) * (size_t)L.m * L.dim) : 0;
@@ -158,8 +159,8 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     L.off_g = take(sizeof(double) * (size_t)L.n);
     L.off_rowv = take(sizeof(double) * (size_t)L.m * 10);   // p[2] pb[2] pa rs[2] rsb (+2 spare)
     L.off_colv = take(sizeof(double) * (size_t)L.n * 10);
-    L.off_rowpart = take(sizeof(double) * (size_t)L.ncb * 2 * (size_t)L.m);
-    L.off_colpart = take(sizeof(double) * (size_t)L.nrb * 2 * (size_t)L.n);
+    L.off_rowpart = take(sizeof(double) * (size_t)L.ncb * (size_t)L.m);
+    L.off_colpart = take(sizeof(double) * (size_t)L.nrb * (size_t)L.n);
     L.off_tiles = take(sizeof(double) * (size_t)L.ntiles * kNS);
     L.off_comb = take(sizeof(double) * (size_t)L.ncomb * kNC);
     L.off_counter = take(sizeof(uint32_t) * 4);
@@ -311,6 +312,7 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
         void *ws = nullptr;
         std::vector<void *> tmp;
         void *pinned = nullptr;
+        std::vector<hipEvent_t> events;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         ~Cleanup()
@@ -321,6 +323,7 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
             for (void *p : tmp) (void)hipFree(p);
             if (ws) (void)hipFree(ws);
             if (pinned) (void)hipHostFree(pinned);
+            for (auto e : events) (void)hipEventDestroy(e);
             if (own && s) (void)hipStreamDestroy(s);
         }
     } cl;
@@ -370,6 +373,7 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
         I.m = l.m;
         I.n = l.n;
         I.ld = l.ld;
+        I.m_alloc = l.m_alloc;
         I.cost = l.cost;
         I.dim = l.dim;
         I.side = l.side;
@@ -441,6 +445,7 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
         for (int k = 0; k < 4; ++k) c.xr[k] = k;
         c.eta = prm.eta0 > 0.0 ? prm.eta0 : 1.0 / std::sqrt((double)(m + n));
         c.omega = prm.omega0 > 0.0 ? prm.omega0 : 1.0;
+        c.tol_eff = tols[i];
         HIP_TRY(hipMemcpyAsync(I.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));   // host staging buffers above are on the stack
     }
@@ -479,13 +484,43 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
 
     HIP_TRY(hipHostMalloc(&cl.pinned, sizeof(Ctl) * count, hipHostMallocDefault));
     Ctl *hc = (Ctl *)cl.pinned;
+    for (int i = 0; i < count; ++i) hc[i].mode = M_INIT;
     // every slot either evaluates a step trial, restarts, or finishes; bound the launches
     const int64_t max_slots = 3 * std::max<int64_t>(prm.max_passes, 1) + 16;
     int64_t launched = 0;
     bool stop_sent = false;
+    std::vector<double> pass_ms(count, 0.0), comb_ms(count, 0.0);
+    std::vector<hipEvent_t> ev;
+    if (prm.profile) {
+        ev.resize(3);
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        cl.events = ev;
+    }
     while (true) {
-        HIP_TRY(hipGraphLaunch(cl.exec, s));
-        launched += slots;
+        if (prm.profile) {
+            // one slot at a time, pass and combine launches bracketed by events
+            HIP_TRY(hipEventRecord(ev[0], s));
+            for (auto &g : B.groups)
+                HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts, d_tiles + g.first, g.count,
+                                    std::min(g.count, kMaxGrid), s));
+            HIP_TRY(hipEventRecord(ev[1], s));
+            HIP_TRY(launch_combine(d_insts, d_combs, B.ncomb_total, comb_grid, s));
+            HIP_TRY(hipEventRecord(ev[2], s));
+            launched += 1;
+            HIP_TRY(hipEventSynchronize(ev[2]));
+            float a = 0.f, b = 0.f;
+            HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+            HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
+            // attribute to every instance still running (single instance in practice)
+            for (int i = 0; i < count; ++i)
+                if (hc[i].mode != M_IDLE) {
+                    pass_ms[i] += a;
+                    comb_ms[i] += b;
+                }
+        } else {
+            HIP_TRY(hipGraphLaunch(cl.exec, s));
+            launched += slots;
+        }
         for (int i = 0; i < count; ++i)
             HIP_TRY(hipMemcpyAsync(hc + i, insts[i].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -541,6 +576,21 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
             r.rel_kkt = c.r_kkt;
             r.eta = c.eta;
             r.omega = c.omega;
+            // algorithmic bytes per element of each pass kind (plan element size b, cost
+            // element size bc, 0 when regenerated): start-point KKT reads C; a trial reads
+            // X and C and writes X+; the full pass also reads and writes the average; the
+            // restart pass reads two plans; verification reads X and C
+            const double b = (double)l.es, bc = l.stored ? (double)l.es : 0.0;
+            const double per[6] = {0.0, bc, 2 * b + bc, 4 * b + bc, 2 * b, b + bc};
+            const double elems = (double)l.m * (double)l.n;
+            double bytes = 0.0;
+            for (int k = 0; k < 6; ++k) {
+                r.mode_passes[k] = c.mcount[k];
+                bytes += per[k] * elems * (double)c.mcount[k];
+            }
+            r.pass_bytes = bytes;
+            r.pass_ms = pass_ms[i];
+            r.combine_ms = comb_ms[i];
         }
     }
     HIP_TRY(hipStreamSynchronize(s));
