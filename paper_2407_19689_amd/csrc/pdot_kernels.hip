@@ -44,22 +44,13 @@ namespace pdot {
 
 // ------------------------------------------------------------------ small helpers
 
-// Butterfly sum over the 64 lanes of a wave.  Every lane ends with the same value and the
-// pairing is fixed, so the result does not depend on timing.
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Every buffer lives in device global memory.  Pointers read out of the instance table
 // are generic pointers; qualifying them as global lets the compiler use global (not flat)
 // memory instructions, whose completion counters do not serialise against scalar loads.
-// (The host compilation pass of this file only type-checks kernels; it gets no qualifier.)
 // The instance and tile tables (and, inside the streaming kernel, the control blocks) do
 // not change while a kernel runs; reading them through the constant address space lets
 // the compiler use scalar loads into SGPRs instead of vector loads into VGPRs.
+// (The host compilation pass of this file only type-checks kernels; it gets no qualifier.)
 #if defined(__HIP_DEVICE_COMPILE__)
 #define PDOT_GLOBAL __attribute__((address_space(1)))
 #define PDOT_CONST __attribute__((address_space(4)))
@@ -541,7 +532,7 @@ void k_pass(const Inst *__restrict__ insts,
 
 // Relative KKT error (Section 3.1 stacked norm, each block over its own scale; kkt_mode 1
 // uses 1 + scale denominators).  out = {rel_P, rel_D, rel_G}.
-__device__ double rel_kkt(const Prm &P, double nb, double nc, double pres2, double dres2,
+__device__ __forceinline__ double rel_kkt(const Prm &P, double nb, double nc, double pres2, double dres2,
                           double pobj, double dobj, double *out)
 {
     const double ap = sqrt(pres2), ad = sqrt(dres2), gap = fabs(pobj - dobj);
@@ -566,7 +557,7 @@ __device__ double rel_kkt(const Prm &P, double nb, double nc, double pres2, doub
 
 enum { ST_RUNNING = -1, ST_OK = 0, ST_NOT_CONVERGED = 4, ST_NUMERIC = 5 };
 
-__device__ void finish(Ctl &c, const Prm &P, int status)
+__device__ __forceinline__ void finish(Ctl &c, const Prm &P, int status)
 {
     c.status = status;
     c.ret_avg = (P.output == 0 && c.cand_avg && c.T > 0 && c.k > 0) ? 1 : 0;
@@ -574,13 +565,16 @@ __device__ void finish(Ctl &c, const Prm &P, int status)
     c.mode = M_VERIFY;
 }
 
-__device__ bool limits_hit(const Ctl &c, const Prm &P)
+__device__ __forceinline__ bool limits_hit(const Ctl &c, const Prm &P)
 {
     return c.T >= P.max_iters || c.passes >= P.max_passes || c.stop;
 }
 
 // Step-size check of the trial (Section 5, adaptive step size).
-__device__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double inter)
+// g_red = (T+1)^-a and g_grow = (T+1)^-b are evaluated by the caller (in parallel with
+// its loads) for the current T.
+__device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double inter,
+                            double g_red, double g_grow)
 {
     c.passes += 1;
     const double eta_used = c.eta;
@@ -590,9 +584,8 @@ __device__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double
         const double den = 2.0 * fabs(inter);
         const double eta_bar = den > 0.0 ? num / den : INFINITY;
         accept = c.eta <= eta_bar;
-        const double tt = (double)(c.T + 1);
-        const double shrink = (1.0 - pow(tt, -P.red_exp)) * eta_bar;
-        const double grow = (1.0 + pow(tt, -P.grow_exp)) * c.eta;
+        const double shrink = (1.0 - g_red) * eta_bar;
+        const double grow = (1.0 + g_grow) * c.eta;
         c.eta = shrink < grow ? shrink : grow;
         if (!(num == num) || !(c.eta == c.eta)) {   // NaN guard
             c.status = ST_NUMERIC;
@@ -625,10 +618,18 @@ __device__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double
     }
 }
 
-__device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const double *ts)
+__device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const double *ts,
+                        double g_red, double g_grow)
 {
     c.kpasses += 1;
-    c.mcount[mode] += 1;
+    switch (mode) {
+    case M_INIT: c.mcount[M_INIT] += 1; break;
+    case M_TRIAL: c.mcount[M_TRIAL] += 1; break;
+    case M_FULL: c.mcount[M_FULL] += 1; break;
+    case M_RESTART: c.mcount[M_RESTART] += 1; break;
+    case M_VERIFY: c.mcount[M_VERIFY] += 1; break;
+    default: break;
+    }
     if (mode == M_INIT) {
         c.norm_b = sqrt(cs[CS_AUX]);
         c.norm_c = sqrt(ts[TS_AUX]);
@@ -648,7 +649,7 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
         return;
     }
     if (mode == M_TRIAL) {
-        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER]);
+        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], g_red, g_grow);
         return;
     }
     if (mode == M_FULL) {
@@ -694,7 +695,7 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
             finish(c, P, ST_NOT_CONVERGED);
             return;
         }
-        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER]);
+        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], g_red, g_grow);
         return;
     }
     if (mode == M_RESTART) {
@@ -705,11 +706,9 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
             c.omega = exp(P.theta * log(dY / dX) + (1.0 - P.theta) * log(c.omega));
         const int cur = c.xr[R_CUR];
         c.xr[R_ANCHOR] = cur;
-        int others[3], no = 0;
-        for (int b = 0; b < 4; ++b)
-            if (b != cur) others[no++] = b;
-        c.xr[R_TRIAL] = others[0];
-        c.xr[R_AVG] = others[1];
+        // the two lowest buffer indices other than the restart point
+        c.xr[R_TRIAL] = cur == 0 ? 1 : 0;
+        c.xr[R_AVG] = cur <= 1 ? 2 : 1;
         c.wsum = 0.0;
         c.k = 0;
         c.restarts += 1;
@@ -748,25 +747,21 @@ __device__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const 
 
 // ------------------------------------------------------------------ combine + control
 
-__device__ __forceinline__ double block_sum(double v, double *sl)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    v = wave_sum(v);
-    __syncthreads();
-    if (lane == 0) sl[wave] = v;
-    __syncthreads();
-    const double r = ((sl[0] + sl[1]) + sl[2]) + sl[3];
-    return r;
-}
-
+// The combine kernel: one work-group per slice of 64 rows or 64 columns of an instance.
+//  1. adds the per-tile partial sums of the slice (waves split the partials, fixed order);
+//  2. per row/column (wave 0): KKT pieces of the current iterate and of the average, the
+//     dual step of the trial, its running average, and the step-size terms;
+//  3. hands its eight slice scalars to the last work-group of the instance (agent-scope
+//     atomic stores and a counter), which reduces them with the tile scalars of the pass
+//     in a fixed order and runs the control of Section 5 for the next slot.
 __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                                                  const CombEntry *__restrict__ ents, int nents)
 {
     __shared__ double part[4][64];
-    __shared__ double sl[8];
-    __shared__ double fin[kNC + kNS];
+    __shared__ double fin[4][kNC + kNS];
     __shared__ int is_last;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
     for (int e = blockIdx.x; e < nents; e += gridDim.x) {
         const CombEntry E = cp(ents)[e];
@@ -780,15 +775,36 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         const int64_t len = rows ? I.m : I.n;
         const int64_t idx = (int64_t)E.start + lane;
         const bool valid = idx < len;
+        const bool sums = mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY;
 
-        // phase 1: add the per-tile partial sums of this slice in a fixed order
+        PDOT_GLOBAL double *pcur = gp(rows ? I.p[st.pv] : I.q[st.pv]);
+        PDOT_GLOBAL double *pnext = gp(rows ? I.p[st.pv ^ 1] : I.q[st.pv ^ 1]);
+        PDOT_GLOBAL double *pbcur = gp(rows ? I.pb[st.pbv] : I.qb[st.pbv]);
+        PDOT_GLOBAL double *pbnext = gp(rows ? I.pb[st.pbv ^ 1] : I.qb[st.pbv ^ 1]);
+        PDOT_GLOBAL double *rscur = gp(rows ? I.rs[st.rsv] : I.cs[st.rsv]);
+        PDOT_GLOBAL double *rsnext = gp(rows ? I.rs[st.rsv ^ 1] : I.cs[st.rsv ^ 1]);
+        PDOT_GLOBAL double *sbar = gp(rows ? I.rsb : I.csb);
+        PDOT_GLOBAL double *anc = gp(rows ? I.pa : I.qa);
+
+        // wave 0 loads its per-entry vectors first; they do not depend on the partials
+        double fi = 0.0, pc0 = 0.0, pb0 = 0.0, rc0 = 0.0, sb0 = 0.0, an0 = 0.0;
+        if (wave == 0 && valid) {
+            fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
+            pc0 = pcur[idx];
+            pb0 = pbcur[idx];
+            rc0 = rscur[idx];
+            if (mode == M_FULL || mode == M_RESTART) sb0 = sbar[idx];
+            if (mode == M_RESTART) an0 = anc[idx];
+        }
+
+        // phase 1: the per-tile partial sums of this slice, in a fixed order
         double sv = 0.0;
-        if (mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY) {
+        if (sums) {
             const int P4 = rows ? I.ncb : I.nrb;
             const PDOT_GLOBAL double *src = gp(rows ? I.rowpart : I.colpart);
             if (valid) {
                 // wave w adds partials w, w+4, w+8, ...; four independent accumulators keep
-                // several loads in flight; the combination order is fixed
+                // several loads in flight
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 int pp = wave;
                 for (; pp + 12 < P4; pp += 16) {
@@ -805,7 +821,6 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             part[wave][lane] = sv;
             __syncthreads();
             if (wave == 0) sv = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
-            __syncthreads();
         }
 
         // phase 2: per-entry vector work (wave 0, one row or column per lane)
@@ -814,41 +829,29 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 #pragma unroll
             for (int s = 0; s < kNC; ++s) acc[s] = 0.0;
             if (valid) {
-                const double fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
-                PDOT_GLOBAL double *pcur = gp(rows ? I.p[st.pv] : I.q[st.pv]);
-                PDOT_GLOBAL double *pnext = gp(rows ? I.p[st.pv ^ 1] : I.q[st.pv ^ 1]);
-                PDOT_GLOBAL double *pbcur = gp(rows ? I.pb[st.pbv] : I.qb[st.pbv]);
-                PDOT_GLOBAL double *pbnext = gp(rows ? I.pb[st.pbv ^ 1] : I.qb[st.pbv ^ 1]);
-                PDOT_GLOBAL double *rscur = gp(rows ? I.rs[st.rsv] : I.cs[st.rsv]);
-                PDOT_GLOBAL double *rsnext = gp(rows ? I.rs[st.rsv ^ 1] : I.cs[st.rsv ^ 1]);
-                PDOT_GLOBAL double *sbar = gp(rows ? I.rsb : I.csb);
-                PDOT_GLOBAL double *anc = gp(rows ? I.pa : I.qa);
                 if (mode == M_INIT) {
                     acc[CS_AUX] = fi * fi;
                 } else if (mode == M_TRIAL || mode == M_FULL) {
                     if (mode == M_FULL) {
                         // KKT of the current iterate: its sums were kept when it was accepted
-                        const double rc = rscur[idx];
-                        double dl = rc - fi;
+                        double dl = rc0 - fi;
                         acc[CS_PRES] = dl * dl;
-                        acc[CS_DOBJ] = fi * pcur[idx];
+                        acc[CS_DOBJ] = fi * pc0;
                         // averaged sums (linear in the plan), same weights as the plan average
-                        const double nb = (st.k == 1) ? rc : (1.0 - st.a_fold) * sbar[idx] + st.a_fold * rc;
+                        const double nb = (st.k == 1) ? rc0 : (1.0 - st.a_fold) * sb0 + st.a_fold * rc0;
                         sbar[idx] = nb;
                         dl = nb - fi;
                         acc[CS_PRESB] = dl * dl;
-                        acc[CS_DOBJB] = fi * pbcur[idx];
+                        acc[CS_DOBJB] = fi * pb0;
                     }
                     // dual step with the extrapolated sums: (2X+ - X) 1 = 2 X+ 1 - X 1, where
                     // X 1 (the current iterate's sums) was kept when X was accepted; the
                     // trial's change of the sums is X+ 1 - X 1
                     const double sigma = st.eta * st.omega;
-                    const double rcur = rscur[idx];
-                    const double sd = sv - rcur;
+                    const double sd = sv - rc0;
                     const double er = sv + sd;
-                    const double pold = pcur[idx];
-                    const double pn = pold + sigma * (fi - er);
-                    const double d = pn - pold;
+                    const double pn = pc0 + sigma * (fi - er);
+                    const double d = pn - pc0;
                     pnext[idx] = pn;
                     rsnext[idx] = sv;
                     acc[CS_DY2] = d * d;
@@ -856,66 +859,72 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                     // tentative running average of the duals for the trial
                     const double w = P.avg_weighting == 1 ? 1.0 : st.eta;
                     const double a2 = w / (st.wsum + w);
-                    pbnext[idx] = (st.k == 0) ? pn : (1.0 - a2) * pbcur[idx] + a2 * pn;
+                    pbnext[idx] = (st.k == 0) ? pn : (1.0 - a2) * pb0 + a2 * pn;
                 } else if (mode == M_RESTART) {
-                    const double pnew = st.cand_avg ? pbcur[idx] : pcur[idx];
-                    const double dd = pnew - anc[idx];
+                    const double pnew = st.cand_avg ? pb0 : pc0;
+                    const double dd = pnew - an0;
                     acc[CS_AUX] = dd * dd;
                     pcur[idx] = pnew;
                     anc[idx] = pnew;
-                    if (st.cand_avg) rscur[idx] = sbar[idx];
+                    if (st.cand_avg) rscur[idx] = sb0;
                 } else if (mode == M_VERIFY) {
-                    const PDOT_GLOBAL double *pret = st.ret_avg ? pbcur : pcur;
                     const double dl = sv - fi;
                     acc[CS_PRES] = dl * dl;
-                    acc[CS_DOBJ] = fi * pret[idx];
+                    acc[CS_DOBJ] = fi * (st.ret_avg ? pb0 : pc0);
                 }
             }
-            // The entry scalars are handed to the last work-group with agent-scope atomic
-            // stores and loads, which are coherent across the chiplets' L2 caches on their
-            // own; no full-cache write-back or invalidation is needed for them.
+            // The entry scalars go to the last work-group with agent-scope atomic stores
+            // and loads, which are coherent across the chiplets' L2 caches on their own; no
+            // full-cache write-back or invalidation is needed for them.
+            double r[kNC];
 #pragma unroll
-            for (int s = 0; s < kNC; ++s) {
-                const double r = wave_sum(acc[s]);
-                if (lane == 0)
-                    __hip_atomic_store(gp(I.combscal) + (int64_t)E.local * kNC + s, r, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            for (int s = 0; s < kNC; ++s) r[s] = wave_sum_to63(acc[s]);
+            if (lane == 63) {
+#pragma unroll
+                for (int s = 0; s < kNC; ++s)
+                    __hip_atomic_store(gp(I.combscal) + (int64_t)E.local * kNC + s, r[s],
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // those stores (same thread) complete before the counter moves
+                __builtin_amdgcn_s_waitcnt(0);
+                const unsigned prev = __hip_atomic_fetch_add(gp(I.counter), 1u, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                is_last = (prev == (unsigned)(I.ncomb - 1)) ? 1 : 0;
             }
-        }
-
-        // phase 3: the last work-group of this instance runs the control
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            // the scalar stores above (same thread) complete before the counter moves
-            __builtin_amdgcn_s_waitcnt(0);
-            const unsigned prev = __hip_atomic_fetch_add(gp(I.counter), 1u, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-            is_last = (prev == (unsigned)(I.ncomb - 1)) ? 1 : 0;
         }
         __syncthreads();
         if (!is_last) continue;
 
+        // phase 3 (last work-group of the instance): reduce every slice and tile scalar in
+        // a fixed order and run the control
+        const double tt = (double)(st.T + 1);
+        const double g_red = pow(tt, -P.red_exp), g_grow = pow(tt, -P.grow_exp);
         double loc[kNC + kNS];
 #pragma unroll
         for (int s = 0; s < kNC + kNS; ++s) loc[s] = 0.0;
         for (int c = threadIdx.x; c < I.ncomb; c += kWG) {
             const PDOT_GLOBAL double *src = gp(I.combscal) + (int64_t)c * kNC;
 #pragma unroll
-            for (int s = 0; s < kNC; ++s) loc[s] += __hip_atomic_load(src + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int s = 0; s < kNC; ++s)
+                loc[s] += __hip_atomic_load(src + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         for (int t = threadIdx.x; t < I.ntiles; t += kWG) {
             const PDOT_GLOBAL double *src = gp(I.tilescal) + (int64_t)t * kNS;
 #pragma unroll
             for (int s = 0; s < kNS; ++s) loc[kNC + s] += src[s];
         }
-        for (int s = 0; s < kNC + kNS; ++s) {
-            const double r = block_sum(loc[s], sl);
-            if (threadIdx.x == 0) fin[s] = r;
+#pragma unroll
+        for (int s = 0; s < kNC + kNS; ++s) loc[s] = wave_sum_to63(loc[s]);
+        if (lane == 63) {
+#pragma unroll
+            for (int s = 0; s < kNC + kNS; ++s) fin[wave][s] = loc[s];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
+            double tot[kNC + kNS];
+            for (int s = 0; s < kNC + kNS; ++s)
+                tot[s] = ((fin[0][s] + fin[1][s]) + fin[2][s]) + fin[3][s];
             Ctl c = *gp(I.ctl);
-            control(c, P, mode, fin, fin + kNC);
+            control(c, P, mode, tot, tot + kNC, g_red, g_grow);
             *gp(I.ctl) = c;
             __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }

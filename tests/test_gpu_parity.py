@@ -1,0 +1,363 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances, and where they come from:
+  * Fixed-step trajectories (constant eta, no restarts): the GPU runs the same arithmetic
+    as the oracle with a different summation order, so the FP64 plan agrees to a few ulps
+    (asserted 1e-13 relative to max|X|).  The FP32 form stores X in FP32 each step: its
+    per-entry error stays at the FP32 unit roundoff level (asserted 1e-6 relative).
+  * Full adaptive solves: PDHG converges to *an* optimum; X and (u, v) are not unique,
+    so the objective, the KKT error and the marginals are compared, never X entrywise.
+    At relative KKT tol both the oracle's and the GPU's objective are within a few tol of
+    OPT (gap and primal residual are each <= tol), in either direction: at matched
+    tol = 1e-6 the objectives are asserted within 5e-6 relative of each other and of the
+    exact LP optimum.  The 1e-6 objective bound itself is asserted at matched tol 1e-9
+    (FP64 form) and for the FP32 form at tol 1e-7 against the oracle at 1e-9 (its FP32
+    storage floor is near 5e-8 in relative KKT).
+  * Stored versus regenerated costs use one cost function, so plans are bit-identical.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2407_19689_amd as P
+from workloads import generators as gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P._abi.load()          # raises if the HIP library is not built
+    torch.cuda.set_device(0)
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def run_dense(C, f, g, prec, **kw):
+    m, n = C.shape
+    X = torch.zeros((m, n), dtype=torch.float64 if prec == P.OT_PREC_FP64 else torch.float32,
+                    device="cuda")
+    u = torch.zeros(m, dtype=torch.float64, device="cuda")
+    v = torch.zeros(n, dtype=torch.float64, device="cuda")
+    pr = P.problem(P.OT_COST_DENSE, m, n, dev(f), dev(g), C=dev(C), X_out=X, u_out=u, v_out=v)
+    kw.setdefault("time_limit_s", 60.0)
+    st, res = P.ot_solve(pr, P.params(precision=prec, **kw))
+    torch.cuda.synchronize()
+    return st, res.as_dict(), X.double().cpu().numpy(), u.cpu().numpy(), v.cpu().numpy()
+
+
+def random_problem(seed, m, n):
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(size=(m, n))
+    f = rng.uniform(0.1, 1, m)
+    f /= f.sum()
+    g = rng.uniform(0.1, 1, n)
+    g /= g.sum()
+    return C, f, g
+
+
+# ----------------------------------------------------------- fixed-step trajectory parity
+
+SHAPES = [(37, 203, 1, 16), (37, 203, 2, 32), (37, 203, 4, 16), (1, 5, 1, 16), (9, 1, 1, 16),
+          (300, 517, 4, 64), (130, 70, 2, 48), (64, 64, 4, 16)]
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+@pytest.mark.parametrize("m,n,vec,rows", SHAPES)
+def test_fixed_step_trajectory_matches_oracle(prec, m, n, vec, rows):
+    """Algorithm 2 with a constant step and no restart: the GPU's 30th iterate equals the
+    oracle's (current iterate returned, output = 1)."""
+    C, f, g = random_problem(m * 1000 + n, m, n)
+    K, eta, omega = 30, 0.5 / np.sqrt(m + n), 1.3
+    common = dict(tol=1e-12, max_iters=K, step_rule=1, restart_rule=2, output=1, eta0=eta,
+                  omega0=omega)
+    Xo, po, qo, ro, _ = oracle.solve(C, f, g, **common)
+    st, res, X, u, v = run_dense(C, f, g, prec, tile_vec=vec, tile_rows=rows, **common)
+    assert st == P.OT_NOT_CONVERGED and res["iterations"] == K
+    scale = np.abs(Xo).max()
+    lim = 1e-13 if prec == P.OT_PREC_FP64 else 1e-6
+    assert np.abs(X - Xo).max() <= lim * scale
+    dual_scale = max(np.abs(po).max(), np.abs(qo).max())
+    assert np.abs(u - po).max() <= lim * dual_scale * 10
+    assert np.abs(v - qo).max() <= lim * dual_scale * 10
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_average_and_candidate_match_oracle(prec):
+    """With output = 0 the returned plan is the restart candidate: the running average when
+    its KKT error is not larger (Section 5).  Same candidate and same average as the
+    oracle (fixed step, no restart, 25 iterations)."""
+    C, f, g = random_problem(7, 45, 77)
+    common = dict(tol=1e-12, max_iters=25, step_rule=1, restart_rule=2, output=0,
+                  eta0=0.6 / np.sqrt(122), omega0=0.8)
+    Xo, po, qo, ro, _ = oracle.solve(C, f, g, **common)
+    st, res, X, u, v = run_dense(C, f, g, prec, **common)
+    assert res["returned_average"] == ro["returned_average"]
+    lim = 1e-13 if prec == P.OT_PREC_FP64 else 1e-6
+    assert np.abs(X - Xo).max() <= lim * np.abs(Xo).max()
+    assert np.abs(u - po).max() <= lim * np.abs(po).max() * 10
+
+
+# ----------------------------------------------------------- full adaptive solves
+
+def highs_opt(C, f, g):
+    from scipy.optimize import linprog
+    from scipy.sparse import csr_matrix
+    m, n = C.shape
+    rows, cols = [], []
+    for i in range(m):
+        for j in range(n):
+            rows += [i, m + j]
+            cols += [i * n + j, i * n + j]
+    A = csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(m + n, m * n))
+    r = linprog(C.reshape(-1), A_eq=A, b_eq=np.concatenate([f, g]), bounds=(0, None),
+                method="highs")
+    assert r.status == 0
+    return r.fun
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_config1_solve_matches_oracle_and_exact_lp(seed, prec):
+    inst = gen.config_instance(1, seed)
+    C = inst.dense_cost()
+    _, _, _, ref, _ = oracle.solve(C, inst.f, inst.g, tol=1e-6)
+    opt = highs_opt(C, inst.f, inst.g)
+    st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, time_limit_s=60.0))
+    torch.cuda.synchronize()
+    assert st == P.OT_OK, P.ot_last_error()
+    assert res["rel_kkt"] <= 1e-6
+    X = out["X"].double().cpu().numpy()
+    k = oracle.kkt(C, inst.f, inst.g, X, out["u"].cpu().numpy(), out["v"].cpu().numpy())
+    assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)          # the oracle confirms the GPU's KKT
+    assert rel(k["objective"], res["objective"]) <= 1e-12
+    assert rel(res["objective"], ref["objective"]) <= 5e-6
+    assert rel(res["objective"], opt) <= 5e-6
+    assert np.all(X >= 0)
+
+
+@pytest.mark.parametrize("prec,tol", [(P.OT_PREC_FP64, 1e-9), (P.OT_PREC_FP32, 1e-7)])
+def test_objective_within_1e6_of_oracle_at_tight_tolerance(prec, tol):
+    for seed in range(3):
+        inst = gen.config_instance(1, seed)
+        C = inst.dense_cost()
+        _, _, _, ref, _ = oracle.solve(C, inst.f, inst.g, tol=1e-9, max_iters=400000)
+        st, res, _ = P.solve_instance(inst, P.params(tol=tol, precision=prec, time_limit_s=60.0))
+        assert st == P.OT_OK, P.ot_last_error()
+        assert res["rel_kkt"] <= tol
+        assert rel(res["objective"], ref["objective"]) <= 1e-6
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", name)) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_config2_grid_1024_matches_oracle(prec):
+    """m = n = 1024 (32x32 blob images, squared pixel cost regenerated on the GPU); the
+    oracle's objectives at tol 1e-6 and 1e-9 are stored in tests/golden (written by
+    tests/golden/make_golden.py, which calls only the oracle)."""
+    gold = golden("config2_oracle.json")
+    inst = gen.config_instance(2, 0)
+    st, res, _ = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, time_limit_s=60.0))
+    assert st == P.OT_OK, P.ot_last_error()
+    assert res["rel_kkt"] <= 1e-6
+    assert rel(res["objective"], gold["objective_tol1e-9"]) <= 5e-6
+    assert rel(res["objective"], gold["objective_tol1e-6"]) <= 5e-6
+
+
+def test_config3_grid_4096_verified_and_bracketed():
+    """Full size of the benchmark (m = n = 4096, FP32 plan, cost regenerated in-kernel):
+    the oracle recomputes the KKT error of the returned triple, and the objective lies in
+    the certified bracket [f.u + g.v^c, <C, round(X)>] (weak duality with the c-transform;
+    Algorithm 3 gives an exactly feasible plan) widened by the tolerance."""
+    inst = gen.config_instance(3, 0)
+    st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=P.OT_PREC_FP32,
+                                                   time_limit_s=120.0))
+    assert st == P.OT_OK, P.ot_last_error()
+    X = out["X"].double().cpu().numpy()
+    u = out["u"].cpu().numpy()
+    v = out["v"].cpu().numpy()
+    C = inst.dense_cost()
+    k = oracle.kkt(C, inst.f, inst.g, X, u, v)
+    assert k["rel_kkt"] <= 1e-6 * 1.001
+    lb = oracle.dual_lower_bound(C, inst.f, inst.g, u)
+    Xf = oracle.round_plan(inst.f, inst.g, X)
+    ub = float((C * Xf).sum())
+    obj = res["objective"]
+    assert lb <= ub
+    assert lb - 5e-6 * obj <= obj <= ub + 5e-6 * obj
+    assert (ub - lb) / obj <= 1e-4
+
+
+# ----------------------------------------------------------- cost sources
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+@pytest.mark.parametrize("which", ["grid", "points_sq", "points_eu"])
+def test_stored_and_regenerated_costs_give_identical_plans(prec, which):
+    if which == "grid":
+        inst = gen.grid_pair(5, 12, tol=1e-6)
+    elif which == "points_sq":
+        inst = gen.points_sqeuclid(5, 90, 300, tol=1e-6)
+    else:
+        inst = gen.gmm_euclid(5, 120, 70, tol=1e-6)
+    outs = []
+    for store in (0, 1):
+        st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec,
+                                                       time_limit_s=60.0), store=store)
+        assert st == P.OT_OK, P.ot_last_error()
+        outs.append((res, out["X"].cpu().numpy()))
+    assert outs[0][0]["iterations"] == outs[1][0]["iterations"]
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_fp64_regenerated_cost_equals_dense_oracle_cost():
+    """The FP64 kernel's cost equals numpy's FP64 cost bit for bit (no contraction), so the
+    dense and regenerated FP64 solves follow the same trajectory."""
+    for inst in (gen.points_sqeuclid(3, 50, 70), gen.grid_pair(3, 10), gen.gmm_euclid(3, 40, 33)):
+        a = P.solve_instance(inst, P.params(tol=1e-6, precision=P.OT_PREC_FP64), dense=True)
+        b = P.solve_instance(inst, P.params(tol=1e-6, precision=P.OT_PREC_FP64), dense=False)
+        assert a[1]["iterations"] == b[1]["iterations"]
+        assert np.array_equal(a[2]["X"].cpu().numpy(), b[2]["X"].cpu().numpy())
+
+
+# ----------------------------------------------------------- degenerate cases
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_single_row_and_single_column_plans_are_forced(prec):
+    rng = np.random.default_rng(9)
+    n = 37
+    C = rng.uniform(size=(1, n))
+    g = rng.uniform(0.1, 1, n)
+    g /= g.sum()
+    st, res, X, u, v = run_dense(C, np.array([1.0]), g, prec, tol=1e-8)
+    assert st == P.OT_OK
+    np.testing.assert_allclose(X[0], g, atol=2e-7)
+    st, res, X, u, v = run_dense(C.T.copy(), g, np.array([1.0]), prec, tol=1e-8)
+    assert st == P.OT_OK
+    np.testing.assert_allclose(X[:, 0], g, atol=2e-7)
+
+
+def test_separable_cost_and_zero_cost():
+    rng = np.random.default_rng(10)
+    m, n = 33, 71
+    a, b = rng.uniform(size=m), rng.uniform(size=n)
+    _, f, g = random_problem(11, m, n)
+    st, res, X, u, v = run_dense(a[:, None] + b[None, :], f, g, P.OT_PREC_FP64, tol=1e-9)
+    assert st == P.OT_OK
+    assert rel(res["objective"], a @ f + b @ g) <= 1e-8
+    # C = 0: the start point X = 0 is infeasible; every feasible plan is optimal with OPT 0
+    st, res, X, u, v = run_dense(np.zeros((m, n)), f, g, P.OT_PREC_FP64, tol=1e-8)
+    assert st == P.OT_OK
+    assert abs(res["objective"]) == 0.0
+    assert res["rel_primal"] <= 1e-8
+
+
+def test_identical_marginals_on_a_metric_cost_have_zero_optimum():
+    inst = gen.grid_pair(21, 9)
+    C = inst.dense_cost()
+    st, res, X, u, v = run_dense(C, inst.f, inst.f.copy(), P.OT_PREC_FP64, tol=1e-8)
+    assert st == P.OT_OK
+    assert res["objective"] <= 1e-7 * C.max()
+
+
+# ----------------------------------------------------------- failure paths
+
+def test_nonfinite_cost_is_reported_numeric():
+    C, f, g = random_problem(3, 20, 30)
+    C[4, 7] = np.nan
+    st, res, X, u, v = run_dense(C, f, g, P.OT_PREC_FP64)
+    assert st == P.OT_ERR_NUMERIC
+
+
+def test_iteration_limit_returns_filled_outputs():
+    C, f, g = random_problem(4, 40, 50)
+    st, res, X, u, v = run_dense(C, f, g, P.OT_PREC_FP32, tol=1e-9, max_iters=5)
+    assert st == P.OT_NOT_CONVERGED
+    assert res["iterations"] == 5 and res["rel_kkt"] > 1e-9
+    assert np.all(np.isfinite(X)) and np.all(np.isfinite(u)) and np.all(np.isfinite(v))
+    k = oracle.kkt(C, f, g, X, u, v)
+    assert rel(k["rel_kkt"], res["rel_kkt"]) <= 1e-9
+
+
+def test_time_limit_stops_the_solve():
+    inst = gen.grid_pair(3, 48)
+    st, res, _ = P.solve_instance(inst, P.params(tol=1e-12, time_limit_s=0.05, graph_slots=16))
+    assert st == P.OT_NOT_CONVERGED
+    assert res["seconds"] < 5.0
+
+
+def test_unbalanced_or_negative_marginals_are_invalid():
+    C, f, g = random_problem(5, 10, 12)
+    st, *_ = run_dense(C, f * 1.001, g, P.OT_PREC_FP64)
+    assert st == P.OT_ERR_INVALID
+    f2 = f.copy()
+    f2[0] = -f2[0]
+    g2 = g * (f2.sum() / g.sum())
+    st, *_ = run_dense(C, f2, g2, P.OT_PREC_FP64)
+    assert st == P.OT_ERR_INVALID
+
+
+# ----------------------------------------------------------- determinism, batch, plumbing
+
+def test_repeated_solves_are_bit_identical():
+    inst = gen.grid_pair(8, 40)
+    a = P.solve_instance(inst, P.params(tol=1e-5))
+    b = P.solve_instance(inst, P.params(tol=1e-5))
+    assert a[1]["iterations"] == b[1]["iterations"]
+    assert np.array_equal(a[2]["X"].cpu().numpy(), b[2]["X"].cpu().numpy())
+    assert np.array_equal(a[2]["u"].cpu().numpy(), b[2]["u"].cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_batch_equals_solo(prec):
+    insts = [gen.gmm_euclid(40 + i, m, n, tol=1e-5)
+             for i, (m, n) in enumerate([(33, 700), (512, 48), (260, 260), (1, 90), (97, 1)])]
+    insts.append(gen.grid_pair(45, 14, tol=1e-5))
+    prm = P.params(tol=1e-5, precision=prec, time_limit_s=60.0)
+    probs, outs = [], []
+    for inst in insts:
+        pr, out = P.problem_from_instance(inst, precision=prec, tol=inst.tol)
+        probs.append(pr)
+        outs.append(out)
+    st, results = P.ot_solve_batch(probs, prm)
+    torch.cuda.synchronize()
+    assert st == P.OT_OK, P.ot_last_error()
+    for inst, out, rb in zip(insts, outs, results):
+        s1, r1, o1 = P.solve_instance(inst, prm, tol=inst.tol)
+        assert s1 == P.OT_OK
+        assert rb.iterations == r1["iterations"] and rb.restarts == r1["restarts"]
+        assert np.array_equal(out["X"].cpu().numpy(), o1["X"].cpu().numpy())
+        assert np.array_equal(out["u"].cpu().numpy(), o1["u"].cpu().numpy())
+
+
+def test_caller_workspace_and_stream():
+    inst = gen.points_sqeuclid(12, 200, 150, tol=1e-6)
+    prm = P.params(tol=1e-6)
+    pr, out = P.problem_from_instance(inst)
+    nbytes = P.ot_workspace_size(pr, prm)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    st, res = P.ot_solve(pr, prm, workspace=ws, stream=stream.cuda_stream)
+    assert st == P.OT_OK
+    s2, r2, o2 = P.solve_instance(inst, prm)
+    assert res.iterations == r2["iterations"]
+    assert np.array_equal(out["X"].cpu().numpy(), o2["X"].cpu().numpy())
+    small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
+    st, _ = P.ot_solve(pr, prm, workspace=small)
+    assert st == P.OT_ERR_OOM
