@@ -238,6 +238,9 @@ __device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, con
 template <typename TX, int VEC, int COST, int MODE>
 __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &tl, double *lds)
 {
+    // Every product and sum below is rounded as written (fused multiply-adds only where
+    // fma() is spelled out), so all kernel variants (cost source, tile shape) round alike.
+#pragma clang fp contract(off)
     constexpr int RU = sizeof(TX) == 4 ? PDOT_RU_F32 : PDOT_RU_F64;   // rows in flight per wave
     constexpr bool kX = MODE != M_INIT;         // reads the plan
     constexpr bool kCost = MODE != M_RESTART;   // needs C
@@ -389,18 +392,18 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                 xb_out[v] = (TX)0;
                 if constexpr (MODE == M_INIT) {
                     const double cm = (colok[v] && i < m) ? cd : 0.0;
-                    s_aux += cm * cm;
+                    s_aux = fma(cm, cm, s_aux);
                     const double nd = fmax((R.pi[u] + qv[v]) - cd, 0.0);
-                    s_dres += nd * nd;
+                    s_dres = fma(nd, nd, s_dres);
                 }
                 if constexpr (MODE == M_RESTART) {
                     const double d = xd - (double)R.an[u][v];
-                    s_aux += d * d;
+                    s_aux = fma(d, d, s_aux);
                 }
                 if constexpr (MODE == M_VERIFY) {
                     const double nd = fmax((R.pi[u] + qv[v]) - cd, 0.0);
-                    s_dres += nd * nd;
-                    s_pobj += cd * xd;
+                    s_dres = fma(nd, nd, s_dres);
+                    s_pobj = fma(cd, xd, s_pobj);
                     rsum[u] += xd;
                     csv[v] += xd;
                 }
@@ -410,26 +413,26 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                     if constexpr (kFold) {
                         // KKT pieces of the current iterate (its duals are p, q)
                         const double ng = fmin(gr, 0.0);
-                        s_dres += ng * ng;
-                        s_pobj += cd * xd;
+                        s_dres = fma(ng, ng, s_dres);
+                        s_pobj = fma(cd, xd, s_pobj);
                         // fold the current iterate into the running average; the averaged
                         // objective uses the value before storage rounding, like the
                         // averaged row and column sums
                         const double xbd = (double)R.b[u][v];
-                        const double xbn = first_fold ? xd : (1.0 - a) * xbd + a * xd;
+                        const double xbn = first_fold ? xd : fma(a, xd, (1.0 - a) * xbd);
                         xb_out[v] = store_avg<TX>(xbn, hrow ^ hcol[v]);
                         const double nb = fmax((R.pbi[u] + qbv[v]) - cd, 0.0);
-                        s_dresb += nb * nb;
-                        s_pobjb += cd * xbn;
+                        s_dresb = fma(nb, nb, s_dresb);
+                        s_pobjb = fma(cd, xbn, s_pobjb);
                     }
-                    const double y = xd - tau * gr;
+                    const double y = fma(-tau, gr, xd);
                     const TX xn = (TX)fmax(y, 0.0);
                     xn_out[v] = xn;
                     const double xnd = (double)xn;
                     const double d = xnd - xd;
                     rsum[u] += xnd;
                     csv[v] += xnd;
-                    s_dx2 += d * d;
+                    s_dx2 = fma(d, d, s_dx2);
                 }
             }
             if (active) {
