@@ -23,6 +23,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("time-to-rel-KKT 1e-6 & PDHG iter/s (HBM GB/s) at m=n=4096; p50/p99 batched")
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2407_19689_amd", "csrc", "pdot_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_grid4096_fp32_traffic.md")
+COPY_BYTES = 1 << 30          # the calibration copy moves 1 GiB each way
 
 
 def log(msg):
@@ -43,6 +46,104 @@ def gpu_solve(P, inst, tol, precision, store, profile=0):
     return dt, res.as_dict()
 
 
+def kernel_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def traffic_probe():
+    """Workload for the two counter runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE): a
+    plain 1 GiB device copy (calibration) and 300 iterations of the benchmark solve."""
+    import torch
+    import paper_2407_19689_amd as P
+    from workloads import generators as gen
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    inst = gen.grid_pair(200, 64)
+    prm = P.params(tol=1e-12, precision=P.OT_PREC_FP32, max_iters=300, time_limit_s=60.0)
+    pr, _ = P.problem_from_instance(inst, precision=P.OT_PREC_FP32, want_plan=False)
+    st, r = P.ot_solve(pr, prm)
+    torch.cuda.synchronize()
+    launches = sum(r.mode_passes)
+    print(json.dumps({"probe": "traffic", "launches": launches,
+                      "algorithmic_bytes_per_launch": r.pass_bytes / launches,
+                      "mode_passes": list(r.mode_passes)}), flush=True)
+
+
+def summarize_traffic(fetch_dir, write_dir, probe_log):
+    """Per-launch HBM traffic of the streaming pass from the two counter runs, each scaled
+    by the counter's reading for the 1 GiB copy; writes the traffic summary in profiles/."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        vals = {}
+        for row in csv.DictReader(open(f)):
+            if row.get("Counter_Name") != counter:
+                continue
+            key = (row["Dispatch_Id"], row["Kernel_Name"])
+            vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+        copy = [v for (i, k), v in vals.items() if "copy" in k.lower() or "elementwise" in k.lower()]
+        kpass = [v for (i, k), v in vals.items() if "k_pass" in k]
+        return max(copy), sum(kpass) / len(kpass), len(kpass)
+
+    probe = [json.loads(x) for x in open(probe_log) if x.startswith('{"probe"')][0]
+    fc, fp, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
+    wc, wp, nw = per_dispatch(write_dir, "WRITE_SIZE")
+    kf, kw = COPY_BYTES / fc, COPY_BYTES / wc          # bytes per counter unit
+    traffic = fp * kf + wp * kw
+    algo = probe["algorithmic_bytes_per_launch"]
+    lines = [
+        "# k_pass (m=n=4096 grid, FP32 plan, cost regenerated): HBM traffic per launch",
+        "",
+        "Counters: `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch), each in its own run:",
+        "",
+        "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --traffic-probe",
+        "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --traffic-probe",
+        "    python3 bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/traffic_probe.log",
+        "",
+        "Calibration: a plain 1 GiB device copy reads {:.0f} and writes {:.0f} counter units,".format(fc, wc),
+        "so one unit is {:.1f} read bytes and {:.1f} written bytes.".format(kf, kw),
+        "",
+        "| quantity | per k_pass launch |",
+        "|---|---|",
+        "| FETCH_SIZE (units, mean of {} dispatches) | {:.0f} |".format(nf, fp),
+        "| WRITE_SIZE (units, mean of {} dispatches) | {:.0f} |".format(nw, wp),
+        "| read bytes (scaled) | {:.4g} |".format(fp * kf),
+        "| written bytes (scaled) | {:.4g} |".format(wp * kw),
+        "| traffic (read + written) | {:.4g} |".format(traffic),
+        "| algorithmic bytes (same launch mix) | {:.4g} |".format(algo),
+        "| traffic / algorithmic | {:.3f} |".format(traffic / algo),
+        "",
+        "traffic_bytes_per_launch: {:.0f}".format(traffic),
+        "algorithmic_bytes_per_launch: {:.0f}".format(algo),
+        "kernel_source_sha256: {}".format(kernel_sha()),
+    ]
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def stored_traffic():
+    """Traffic per launch from the committed counter summary, or None when the kernel
+    source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith(("#", "|", " ")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_sha():
+        return None
+    return float(vals["traffic_bytes_per_launch"]), float(vals["algorithmic_bytes_per_launch"])
+
+
 def cpu_baseline(inst, budget_s=15.0):
     """The FP64 oracle on the host cores: PDHG iterations/s over the first iterations of
     the same instance (a bounded sample; the full solve would take hours)."""
@@ -50,11 +151,15 @@ def cpu_baseline(inst, budget_s=15.0):
     import oracle
     C = inst.dense_cost()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    # calibrate with 2 iterations, then run about budget_s of work
+    # calibrate the per-iteration time (a 6-iteration run minus a 1-iteration run, which
+    # removes the set-up), then run about budget_s of work
     t = time.perf_counter()
-    oracle.solve(C, inst.f, inst.g, tol=1e-12, max_iters=2, nthreads=threads)
-    per = (time.perf_counter() - t) / 2.0
-    iters = max(2, int(budget_s / max(per, 1e-6)))
+    oracle.solve(C, inst.f, inst.g, tol=1e-12, max_iters=1, nthreads=threads)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.solve(C, inst.f, inst.g, tol=1e-12, max_iters=6, nthreads=threads)
+    per = max((time.perf_counter() - t - t1) / 5.0, 1e-6)
+    iters = max(2, int(budget_s / per))
     t = time.perf_counter()
     _, _, _, res, _ = oracle.solve(C, inst.f, inst.g, tol=1e-12, max_iters=iters, nthreads=threads)
     dt = time.perf_counter() - t
@@ -72,7 +177,16 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the workload of the counter runs (see profiles/)")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_LOG"))
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
+    if args.traffic_probe:
+        traffic_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(instances shard across GPUs without communication; see the design notes)",
@@ -115,8 +229,13 @@ def main():
     log(f"profiled solve: {launches} pass launches, avg {avg_ms * 1e3:.2f} us, "
         f"{avg_bytes / 1e6:.1f} MB algorithmic, {achieved:.0f} GB/s; combine avg "
         f"{rp['combine_ms'] / max(launches, 1) * 1e3:.2f} us")
+    st_tr = stored_traffic()
+    traffic = None
+    if st_tr is not None:
+        # traffic measured per launch of the counter probe's launch mix, scaled to this mix
+        traffic = round(st_tr[0] / st_tr[1] * avg_bytes)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_pass<float,4,grid-sqeuclid>", "avg_launch_us": round(avg_ms * 1e3, 3),
             "algorithmic_bytes_per_launch": round(avg_bytes), "launches": launches,
             "passes_by_kind": {"init": rp["mode_passes"][1], "trial": rp["mode_passes"][2],

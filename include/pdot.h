@@ -97,6 +97,8 @@ typedef struct {
     void *X_out;         /* nullable; m x n contiguous, FP64 or FP32 per precision   */
     double *u_out;       /* nullable; m, the row duals p of the returned iterate      */
     double *v_out;       /* nullable; n, the column duals q                          */
+    int32_t tile_vec;    /* > 0 overrides ot_params.tile_vec for this instance       */
+    int32_t tile_rows;   /* > 0 overrides ot_params.tile_rows for this instance      */
 } ot_problem;
 
 /* Solver parameters.  Defaults (ot_params_default) are the paper's constants:
@@ -181,6 +183,63 @@ ot_status ot_solve(const ot_problem *prob, const ot_params *prm, ot_result *res,
  * converged, otherwise the first non-OK instance status. */
 ot_status ot_solve_batch(const ot_problem *probs, int32_t count, const ot_params *prm,
                          ot_result *res, void *stream);
+
+/* ---- serving: continuous batching of arriving solves --------------------------------
+ *
+ * A server owns one device arena of hbm_budget_bytes and a scheduler thread.  Submitted
+ * problems wait in a FIFO queue; the scheduler admits the head of the queue whenever it
+ * has a free slot (at most max_active instances) and its workspace fits in the arena, so
+ * requests that arrive while others run join the running set between graph launches of
+ * iteration slots.  Every slot of a launch advances all running instances together (one
+ * streaming-pass launch per kernel variant and one combine launch), and each instance's
+ * arithmetic is exactly that of a solo ot_solve with the same parameters and tile shape,
+ * so its result does not depend on the mix.  Iterates stay in device memory from
+ * admission to completion; finished instances release their slot and arena space.
+ *
+ * Callers: one server per device.  ot_server_submit copies the inputs (f, g, costs or
+ * coordinates; host or device pointers) before it returns; the output pointers of the
+ * problem must stay valid until its completion has been returned by ot_server_poll.
+ */
+typedef struct ot_server ot_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;   /* arena size; a request larger than it is rejected (BUSY) */
+    int32_t max_active;        /* running instances at most (>= 1)                       */
+    int32_t max_queue;         /* queued requests at most, 0 = unbounded                 */
+    double block_ms;           /* target duration of one graph launch, 0 = 2 ms          */
+    ot_params params;          /* solver parameters shared by all requests               */
+} ot_server_cfg;
+
+typedef struct {
+    uint64_t ticket;
+    ot_result result;          /* result.status is the request's status                  */
+    double t_submit, t_admit, t_done;   /* seconds since the server was created          */
+} ot_completion;
+
+/* Create a server on the current HIP device; starts its scheduler thread. */
+ot_status ot_server_create(const ot_server_cfg *cfg, ot_server **out);
+
+/* Queue a problem; *ticket identifies its completion.  OT_ERR_BUSY if the queue is full or
+ * the problem can never fit in the arena; OT_ERR_INVALID for an invalid problem. */
+ot_status ot_server_submit(ot_server *srv, const ot_problem *prob, uint64_t *ticket);
+
+/* Move up to max finished requests into out (completion order); *n_out is the count. */
+ot_status ot_server_poll(ot_server *srv, ot_completion *out, int32_t max, int32_t *n_out);
+
+/* Block until every submitted request has completed or timeout_s elapsed (<= 0: no
+ * limit); OT_NOT_CONVERGED on timeout. */
+ot_status ot_server_drain(ot_server *srv, double timeout_s);
+
+/* Counters: submitted, admitted, completed, currently running, queued, arena bytes in use,
+ * graph launches, and the largest number of instances that ran together. */
+typedef struct {
+    int64_t submitted, admitted, completed, running, queued;
+    int64_t arena_used, arena_peak, launches, max_running;
+} ot_server_stats;
+ot_status ot_server_get_stats(ot_server *srv, ot_server_stats *out);
+
+/* Stop the scheduler (running and queued requests are abandoned) and free everything. */
+ot_status ot_server_destroy(ot_server *srv);
 
 /* Message for the last failing call on this thread ("" if none). */
 const char *ot_last_error(void);

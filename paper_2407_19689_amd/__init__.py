@@ -18,12 +18,13 @@ from ._abi import (  # noqa: F401
     OT_OK, OT_ERR_INVALID, OT_ERR_OOM, OT_ERR_DEVICE, OT_NOT_CONVERGED, OT_ERR_NUMERIC,
     OT_ERR_BUSY, OT_PREC_FP64, OT_PREC_FP32, OT_COST_DENSE, OT_COST_POINTS_SQEUCLID,
     OT_COST_POINTS_EUCLID, OT_COST_GRID_SQEUCLID, OtCost, OtParams, OtProblem, OtResult,
-    STATUS_NAMES,
+    OtServerCfg, OtCompletion, OtServerStats, STATUS_NAMES,
 )
 
 __all__ = ["ot_params_default", "ot_workspace_size", "ot_solve", "ot_solve_batch",
-           "ot_last_error", "ot_version", "params", "problem", "solve_instance",
-           "problem_from_instance"]
+           "ot_last_error", "ot_version", "ot_server_create", "ot_server_submit",
+           "ot_server_poll", "ot_server_drain", "ot_server_get_stats", "ot_server_destroy",
+           "params", "problem", "solve_instance", "problem_from_instance", "Server"]
 
 
 def _ptr(a):
@@ -74,7 +75,8 @@ class Problem:
 
 
 def problem(kind, m, n, f, g, C=None, ldc=None, x=None, y=None, side=0, scale=1.0,
-            store=0, tol=0.0, X_out=None, u_out=None, v_out=None) -> Problem:
+            store=0, tol=0.0, X_out=None, u_out=None, v_out=None, tile_vec=0,
+            tile_rows=0) -> Problem:
     """Build an ot_problem from torch tensors or numpy arrays (host or device)."""
     for a, nm in ((f, "f"), (g, "g"), (C, "C"), (x, "x"), (y, "y"), (u_out, "u_out"),
                   (v_out, "v_out")):
@@ -101,6 +103,8 @@ def problem(kind, m, n, f, g, C=None, ldc=None, x=None, y=None, side=0, scale=1.
     pr.X_out = _ptr(X_out)
     pr.u_out = _ptr(u_out)
     pr.v_out = _ptr(v_out)
+    pr.tile_vec = tile_vec
+    pr.tile_rows = tile_rows
     return Problem(pr, [f, g, C, x, y, X_out, u_out, v_out])
 
 
@@ -129,6 +133,94 @@ def ot_solve_batch(probs, prm: OtParams, stream=None):
     return int(st), list(res)
 
 
+def ot_server_create(hbm_budget_bytes, max_active=64, max_queue=0, block_ms=0.0, prm=None):
+    """Returns (status, handle)."""
+    cfg = OtServerCfg()
+    cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+    cfg.max_active = max_active
+    cfg.max_queue = max_queue
+    cfg.block_ms = block_ms
+    cfg.params = prm if prm is not None else ot_params_default()
+    h = ct.c_void_p()
+    st = _abi.load().ot_server_create(ct.byref(cfg), ct.byref(h))
+    return int(st), h
+
+
+def ot_server_submit(handle, prob: Problem):
+    """Returns (status, ticket)."""
+    t = ct.c_uint64()
+    st = _abi.load().ot_server_submit(handle, ct.byref(prob.raw), ct.byref(t))
+    return int(st), int(t.value)
+
+
+def ot_server_poll(handle, max_n=256):
+    """Returns (status, [OtCompletion])."""
+    buf = (OtCompletion * max_n)()
+    n = ct.c_int32()
+    st = _abi.load().ot_server_poll(handle, buf, max_n, ct.byref(n))
+    return int(st), [buf[i] for i in range(n.value)]
+
+
+def ot_server_drain(handle, timeout_s=0.0):
+    return int(_abi.load().ot_server_drain(handle, timeout_s))
+
+
+def ot_server_get_stats(handle):
+    o = OtServerStats()
+    st = _abi.load().ot_server_get_stats(handle, ct.byref(o))
+    return int(st), {k: getattr(o, k) for k, _ in OtServerStats._fields_}
+
+
+def ot_server_destroy(handle):
+    return int(_abi.load().ot_server_destroy(handle))
+
+
+class Server:
+    """Owner of an ot_server handle that keeps every submitted problem's buffers alive until
+    its completion has been polled."""
+
+    def __init__(self, hbm_budget_bytes, max_active=64, max_queue=0, block_ms=0.0, prm=None, **kw):
+        if prm is None:
+            prm = params(**kw)
+        st, self.handle = ot_server_create(hbm_budget_bytes, max_active, max_queue, block_ms, prm)
+        if st != OT_OK:
+            raise RuntimeError(f"ot_server_create: {STATUS_NAMES.get(st)} {ot_last_error()}")
+        self.live = {}
+
+    def submit(self, prob: Problem):
+        st, t = ot_server_submit(self.handle, prob)
+        if st == OT_OK:
+            self.live[t] = prob
+        return st, t
+
+    def poll(self, max_n=256):
+        st, out = ot_server_poll(self.handle, max_n)
+        res = []
+        for c in out:
+            d = c.result.as_dict()
+            d.update(ticket=c.ticket, t_submit=c.t_submit, t_admit=c.t_admit, t_done=c.t_done)
+            res.append(d)
+            self.live.pop(c.ticket, None)
+        return res
+
+    def drain(self, timeout_s=0.0):
+        return ot_server_drain(self.handle, timeout_s)
+
+    def stats(self):
+        return ot_server_get_stats(self.handle)[1]
+
+    def close(self):
+        if self.handle:
+            ot_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def ot_last_error() -> str:
     return _abi.load().ot_last_error().decode()
 
@@ -147,7 +239,7 @@ _KINDS = {
 
 
 def problem_from_instance(inst, device="cuda", precision=OT_PREC_FP32, store=0, dense=False,
-                          tol=0.0, want_plan=True):
+                          tol=0.0, want_plan=True, tile_vec=0, tile_rows=0):
     """Place an instance (attributes m, n, f, g, kind, x, y, side, scale, dense_cost())
     in device memory with torch and allocate the outputs.  Returns (Problem, outputs)."""
     import torch
@@ -161,17 +253,18 @@ def problem_from_instance(inst, device="cuda", precision=OT_PREC_FP32, store=0, 
     out = {"X": X, "u": u, "v": v}
     if dense or inst.kind not in _KINDS:
         C = torch.as_tensor(np.ascontiguousarray(inst.dense_cost(), dtype=np.float64), device=dev)
-        pr = problem(OT_COST_DENSE, inst.m, inst.n, f, g, C=C, tol=tol, X_out=X, u_out=u, v_out=v)
+        pr = problem(OT_COST_DENSE, inst.m, inst.n, f, g, C=C, tol=tol, X_out=X, u_out=u, v_out=v,
+                     tile_vec=tile_vec, tile_rows=tile_rows)
         return pr, out
     kind = _KINDS[inst.kind]
     if kind == OT_COST_GRID_SQEUCLID:
         pr = problem(kind, inst.m, inst.n, f, g, side=inst.side, scale=inst.scale, store=store,
-                     tol=tol, X_out=X, u_out=u, v_out=v)
+                     tol=tol, X_out=X, u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows)
     else:
         x = torch.as_tensor(np.ascontiguousarray(inst.x, dtype=np.float64), device=dev)
         y = torch.as_tensor(np.ascontiguousarray(inst.y, dtype=np.float64), device=dev)
         pr = problem(kind, inst.m, inst.n, f, g, x=x, y=y, store=store, tol=tol, X_out=X,
-                     u_out=u, v_out=v)
+                     u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows)
     return pr, out
 
 

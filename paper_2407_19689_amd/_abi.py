@@ -59,6 +59,8 @@ class OtProblem(ct.Structure):
         ("X_out", ct.c_void_p),
         ("u_out", ct.c_void_p),
         ("v_out", ct.c_void_p),
+        ("tile_vec", ct.c_int32),
+        ("tile_rows", ct.c_int32),
     ]
 
 
@@ -122,6 +124,40 @@ class OtResult(ct.Structure):
         return d
 
 
+class OtServerCfg(ct.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ct.c_size_t),
+        ("max_active", ct.c_int32),
+        ("max_queue", ct.c_int32),
+        ("block_ms", ct.c_double),
+        ("params", OtParams),
+    ]
+
+
+class OtCompletion(ct.Structure):
+    _fields_ = [
+        ("ticket", ct.c_uint64),
+        ("result", OtResult),
+        ("t_submit", ct.c_double),
+        ("t_admit", ct.c_double),
+        ("t_done", ct.c_double),
+    ]
+
+
+class OtServerStats(ct.Structure):
+    _fields_ = [
+        ("submitted", ct.c_int64),
+        ("admitted", ct.c_int64),
+        ("completed", ct.c_int64),
+        ("running", ct.c_int64),
+        ("queued", ct.c_int64),
+        ("arena_used", ct.c_int64),
+        ("arena_peak", ct.c_int64),
+        ("launches", ct.c_int64),
+        ("max_running", ct.c_int64),
+    ]
+
+
 # Every symbol the header declares, with (restype, argtypes).
 SIGNATURES = {
     "ot_params_default": (None, [ct.POINTER(OtParams)]),
@@ -130,6 +166,13 @@ SIGNATURES = {
                             ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ot_solve_batch": (ct.c_int, [ct.POINTER(OtProblem), ct.c_int32, ct.POINTER(OtParams),
                                   ct.POINTER(OtResult), ct.c_void_p]),
+    "ot_server_create": (ct.c_int, [ct.POINTER(OtServerCfg), ct.POINTER(ct.c_void_p)]),
+    "ot_server_submit": (ct.c_int, [ct.c_void_p, ct.POINTER(OtProblem), ct.POINTER(ct.c_uint64)]),
+    "ot_server_poll": (ct.c_int, [ct.c_void_p, ct.POINTER(OtCompletion), ct.c_int32,
+                                  ct.POINTER(ct.c_int32)]),
+    "ot_server_drain": (ct.c_int, [ct.c_void_p, ct.c_double]),
+    "ot_server_get_stats": (ct.c_int, [ct.c_void_p, ct.POINTER(OtServerStats)]),
+    "ot_server_destroy": (ct.c_int, [ct.c_void_p]),
     "ot_last_error": (ct.c_char_p, []),
     "ot_version": (ct.c_char_p, []),
 }

@@ -19,6 +19,7 @@
 // Row sums are wave reductions; column sums stay in registers over the tile's rows, are
 // combined across the four waves in LDS and written as one partial row per tile; k_combine
 // adds the partials in a fixed order (deterministic, no floating-point atomics).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -510,11 +511,14 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
     }
 }
 
+// The tile count is read from device memory, so a captured graph stays valid when the
+// host repacks the tile table between launches (instances joining or finishing).
 template <typename TX, int VEC, int COST>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PDOT_PASS_WAVES)))
-void k_pass(const Inst *__restrict__ insts,
-                                              const Tile *__restrict__ tiles, int ntiles)
+void k_pass(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
+            const int32_t *__restrict__ count)
 {
+    const int ntiles = *cp(count);
     __shared__ double lds[3 * 2 * 4 * 64 + 4 * kNS];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = cp(tiles)[t];
@@ -758,8 +762,10 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
 //     atomic stores and a counter), which reduces them with the tile scalars of the pass
 //     in a fixed order and runs the control of Section 5 for the next slot.
 __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
-                                                 const CombEntry *__restrict__ ents, int nents)
+                                                 const CombEntry *__restrict__ ents,
+                                                 const int32_t *__restrict__ count)
 {
+    const int nents = *cp(count);
     __shared__ double part[4][64];
     __shared__ double fin[4][kNC + kNS];
     __shared__ int is_last;
@@ -972,40 +978,55 @@ __global__ __launch_bounds__(kWG) void k_materialize(TX *__restrict__ dst, int64
 
 namespace pdot {
 
+// Launch of the streaming pass.  With events (profiling), the events are stamped with the
+// kernel's own start and end (hipExtLaunchKernel), not with the enqueue times.
+template <typename K>
+static hipError_t launch_k(K kernel, int grid, const Inst *insts, const Tile *tiles,
+                           const int32_t *count, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, tiles, count);
+    else
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, insts, tiles, count);
+    return hipGetLastError();
+}
+
 template <typename TX, int VEC>
-static hipError_t launch_pass_vec(int cost, const Inst *insts, const Tile *tiles, int ntiles,
-                                  int grid, hipStream_t s)
+static hipError_t launch_pass_vec(int cost, const Inst *insts, const Tile *tiles,
+                                  const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0,
+                                  hipEvent_t ev1)
 {
     switch (cost) {
-    case C_STORED: hipLaunchKernelGGL((k_pass<TX, VEC, C_STORED>), dim3(grid), dim3(kWG), 0, s, insts, tiles, ntiles); break;
-    case C_PTS_SQ: hipLaunchKernelGGL((k_pass<TX, VEC, C_PTS_SQ>), dim3(grid), dim3(kWG), 0, s, insts, tiles, ntiles); break;
-    case C_PTS_EU: hipLaunchKernelGGL((k_pass<TX, VEC, C_PTS_EU>), dim3(grid), dim3(kWG), 0, s, insts, tiles, ntiles); break;
-    case C_GRID_SQ: hipLaunchKernelGGL((k_pass<TX, VEC, C_GRID_SQ>), dim3(grid), dim3(kWG), 0, s, insts, tiles, ntiles); break;
+    case C_STORED: return launch_k(k_pass<TX, VEC, C_STORED>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_PTS_SQ: return launch_k(k_pass<TX, VEC, C_PTS_SQ>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_PTS_EU: return launch_k(k_pass<TX, VEC, C_PTS_EU>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_SQ: return launch_k(k_pass<TX, VEC, C_GRID_SQ>, grid, insts, tiles, ntiles, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename TX>
 static hipError_t launch_pass_t(int vec, int cost, const Inst *insts, const Tile *tiles,
-                                int ntiles, int grid, hipStream_t s)
+                                const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0,
+                                hipEvent_t ev1)
 {
     switch (vec) {
-    case 1: return launch_pass_vec<TX, 1>(cost, insts, tiles, ntiles, grid, s);
-    case 2: return launch_pass_vec<TX, 2>(cost, insts, tiles, ntiles, grid, s);
-    case 4: return launch_pass_vec<TX, 4>(cost, insts, tiles, ntiles, grid, s);
+    case 1: return launch_pass_vec<TX, 1>(cost, insts, tiles, ntiles, grid, s, ev0, ev1);
+    case 2: return launch_pass_vec<TX, 2>(cost, insts, tiles, ntiles, grid, s, ev0, ev1);
+    case 4: return launch_pass_vec<TX, 4>(cost, insts, tiles, ntiles, grid, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Tile *tiles,
-                       int ntiles, int grid, hipStream_t s)
+                       const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1)
 {
-    return fp32 ? launch_pass_t<float>(vec, cost, insts, tiles, ntiles, grid, s)
-                : launch_pass_t<double>(vec, cost, insts, tiles, ntiles, grid, s);
+    return fp32 ? launch_pass_t<float>(vec, cost, insts, tiles, ntiles, grid, s, ev0, ev1)
+                : launch_pass_t<double>(vec, cost, insts, tiles, ntiles, grid, s, ev0, ev1);
 }
 
-hipError_t launch_combine(const Inst *insts, const CombEntry *ents, int nents, int grid,
+hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
                           hipStream_t s)
 {
     hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, insts, ents, nents);

@@ -1,21 +1,32 @@
 // Host runtime and C ABI of the restarted-PDHG optimal-transport library (include/pdot.h).
 //
-// A solve is a batch of one or more instances sharing one workspace.  The runtime lays out
-// every instance's buffers, materialises stored costs, writes the device-resident control
-// blocks, captures a HIP graph of `slots` iteration slots (each: one streaming-pass launch
-// per kernel variant present in the batch, then one combine launch), and relaunches that
-// graph until every instance reports idle.  All decisions of the method (Section 5 of
-// the paper: restart candidate, restart conditions, step-size check, primal weight,
-// termination) are taken on the device; the host only reads the mode words between
-// graph launches and enforces the wall-clock limit.
+// Everything runs through one Engine: a device arena holding every admitted instance's
+// buffers and the engine tables, a set of running instances, and a HIP graph of `slots`
+// iteration slots.  A slot is one streaming-pass launch per kernel variant (precision,
+// columns per lane, cost source) present among the running instances, then one combine
+// launch.  The tables (instance descriptors, tiles grouped by variant, combine entries)
+// live in device memory and their lengths are read by the kernels from device memory, so
+// the host can repack them between graph launches (instances finishing, or joining in the
+// server) without touching the graph; it is captured again only when the variant layout
+// of the tile table changes.  All decisions of the method (Section 5 of the paper:
+// restart candidate, restart conditions, step-size check, primal weight, termination)
+// are taken on the device; the host reads the mode words between graph launches,
+// retires finished instances and enforces wall-clock limits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pdot.h"
@@ -23,8 +34,9 @@
 
 namespace pdot {
 hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Tile *tiles,
-                       int ntiles, int grid, hipStream_t s);
-hipError_t launch_combine(const Inst *insts, const CombEntry *ents, int nents, int grid,
+                       const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
+hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
                           hipStream_t s);
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,
                               const double *src, int64_t ldc, const double *xs, const double *ys,
@@ -50,12 +62,27 @@ ot_status fail(ot_status st, const std::string &msg)
             return fail(OT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define OT_TRY(expr)                 \
+    do {                             \
+        ot_status s_ = (expr);       \
+        if (s_ != OT_OK) return s_;  \
+    } while (0)
+
 constexpr size_t kAlign = 256;
 constexpr int kMaxGrid = 4096;
+constexpr int kMaxGroups = 24;   // precisions x columns-per-lane x cost sources
+
+enum { ST_RUNNING = -1 };
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Per-instance layout inside the workspace.
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ per-instance layout
+
 struct Layout {
     int64_t m = 0, n = 0, ld = 0, m_alloc = 0;
     int fp32 = 1, vec = 4, rows = 64, ncb = 0, nrb = 0, ntiles = 0, ncomb = 0;
@@ -133,10 +160,10 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     default:
         return fail(OT_ERR_INVALID, "unknown cost kind");
     }
-    L.vec = prm.tile_vec ? prm.tile_vec : default_vec(pb.n);
+    L.vec = pb.tile_vec > 0 ? pb.tile_vec : (prm.tile_vec ? prm.tile_vec : default_vec(pb.n));
     if (L.vec != 1 && L.vec != 2 && L.vec != 4) return fail(OT_ERR_INVALID, "tile_vec must be 1, 2 or 4");
     L.ncb = (int)((pb.n + 64 * L.vec - 1) / (64 * L.vec));
-    L.rows = prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb);
+    L.rows = pb.tile_rows > 0 ? pb.tile_rows : (prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb));
     if (L.rows < 16 || L.rows % 16) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 16");
     L.nrb = (int)((pb.m + L.rows - 1) / L.rows);
     const int64_t nt = (int64_t)L.ncb * L.nrb;
@@ -157,8 +184,8 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     L.off_ys = L.dim ? take(sizeof(double) * (size_t)L.n * L.dim) : 0;
     L.off_f = take(sizeof(double) * (size_t)L.m);
     L.off_g = take(sizeof(double) * (size_t)L.n);
-    L.off_rowv = take(sizeof(double) * (size_t)L.m * 10);   // p[2] pb[2] pa rs[2] rsb (+2 spare)
-    L.off_colv = take(sizeof(double) * (size_t)L.n * 10);
+    L.off_rowv = take(sizeof(double) * (size_t)L.m * 8);   // p[2] pb[2] pa rs[2] rsb
+    L.off_colv = take(sizeof(double) * (size_t)L.n * 8);
     L.off_rowpart = take(sizeof(double) * (size_t)L.ncb * (size_t)L.m);
     L.off_colpart = take(sizeof(double) * (size_t)L.nrb * (size_t)L.n);
     L.off_tiles = take(sizeof(double) * (size_t)L.ntiles * kNS);
@@ -193,6 +220,13 @@ Prm device_params(const ot_params &p, double tol)
     return d;
 }
 
+ot_status check_params(const ot_params &prm)
+{
+    if (!(prm.tol > 0.0)) return fail(OT_ERR_INVALID, "tol must be > 0");
+    if (prm.max_iters < 0 || prm.max_passes < 0) return fail(OT_ERR_INVALID, "negative limits");
+    return OT_OK;
+}
+
 bool is_device_ptr(const void *p)
 {
     if (!p) return false;
@@ -204,171 +238,373 @@ bool is_device_ptr(const void *p)
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-// Copy n doubles from a host or device pointer to host memory.
-ot_status fetch_host(const double *src, size_t count, std::vector<double> &out, hipStream_t s)
+// A non-blocking stream of the calling thread for small host fetches: the legacy stream
+// must not be used while another thread (the server's scheduler) captures a graph.
+ot_status helper_stream(hipStream_t *out)
+{
+    thread_local hipStream_t s = nullptr;
+    thread_local int dev = -1;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (!s || dev != cur) {
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        dev = cur;
+    }
+    *out = s;
+    return OT_OK;
+}
+
+// Copy count doubles from a host or device pointer into host memory.
+ot_status fetch_host(const double *src, size_t count, std::vector<double> &out)
 {
     out.resize(count);
     if (count == 0) return OT_OK;
     if (is_device_ptr(src)) {
-        HIP_TRY(hipMemcpyAsync(out.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        hipStream_t hs = nullptr;
+        OT_TRY(helper_stream(&hs));
+        HIP_TRY(hipMemcpyAsync(out.data(), src, count * sizeof(double), hipMemcpyDeviceToHost, hs));
+        HIP_TRY(hipStreamSynchronize(hs));
     } else {
         memcpy(out.data(), src, count * sizeof(double));
     }
     return OT_OK;
 }
 
-struct Batch {
-    std::vector<Layout> L;
-    std::vector<size_t> base;   // workspace offset of every instance
-    size_t inst_tab = 0, tile_tab = 0, comb_tab = 0, total = 0;
-    int ntiles_total = 0, ncomb_total = 0;
-    struct Group { int fp32, vec, cost, first, count; };
-    std::vector<Group> groups;
-    std::vector<Tile> tiles;
-    std::vector<CombEntry> combs;
-};
-
-ot_status plan_batch(const ot_problem *probs, int count, const ot_params &prm, Batch &B)
+ot_status validate_marginals(const std::vector<double> &f, const std::vector<double> &g)
 {
-    B.L.resize(count);
-    B.base.resize(count);
-    size_t off = 0;
-    for (int i = 0; i < count; ++i) {
-        ot_status st = plan_instance(probs[i], prm, B.L[i]);
-        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
-        B.base[i] = off;
-        off = align_up(off + B.L[i].bytes);
-    }
-    // tiles grouped by kernel variant; every tile knows its instance and local index
-    struct Key { int fp32, vec, cost; };
-    std::vector<Key> keys;
-    for (int i = 0; i < count; ++i) {
-        Key k{B.L[i].fp32, B.L[i].vec, B.L[i].cost};
-        bool seen = false;
-        for (auto &q : keys) seen |= (q.fp32 == k.fp32 && q.vec == k.vec && q.cost == k.cost);
-        if (!seen) keys.push_back(k);
-    }
-    for (auto &k : keys) {
-        Batch::Group g{k.fp32, k.vec, k.cost, (int)B.tiles.size(), 0};
-        for (int i = 0; i < count; ++i) {
-            const Layout &l = B.L[i];
-            if (l.fp32 != k.fp32 || l.vec != k.vec || l.cost != k.cost) continue;
-            for (int rb = 0; rb < l.nrb; ++rb)
-                for (int cb = 0; cb < l.ncb; ++cb)
-                    B.tiles.push_back(Tile{i, rb, cb, rb * l.ncb + cb});
-        }
-        g.count = (int)B.tiles.size() - g.first;
-        B.groups.push_back(g);
-    }
-    for (int i = 0; i < count; ++i) {
-        const Layout &l = B.L[i];
-        int local = 0;
-        for (int64_t r = 0; r < l.m; r += kCombEntries) B.combs.push_back(CombEntry{i, 0, (int)r, local++});
-        for (int64_t c = 0; c < l.n; c += kCombEntries) B.combs.push_back(CombEntry{i, 1, (int)c, local++});
-    }
-    B.ntiles_total = (int)B.tiles.size();
-    B.ncomb_total = (int)B.combs.size();
-    B.inst_tab = off;
-    off = align_up(off + sizeof(Inst) * (size_t)count);
-    B.tile_tab = off;
-    off = align_up(off + sizeof(Tile) * B.tiles.size());
-    B.comb_tab = off;
-    off = align_up(off + sizeof(CombEntry) * B.combs.size());
-    B.total = off;
+    if (!finite_nonneg(f) || !finite_nonneg(g))
+        return fail(OT_ERR_INVALID, "f and g must be finite and >= 0");
+    double sf = 0.0, sg = 0.0;
+    for (double v : f) sf += v;
+    for (double v : g) sg += v;
+    if (!(std::fabs(sf - sg) <= 1e-12 * std::max(sf, sg))) return fail(OT_ERR_INVALID, "sum f != sum g");
     return OT_OK;
 }
 
-int auto_slots(const Batch &B)
-{
-    // about 2 ms of streaming per graph launch at roughly 5 TB/s, 16..512 slots
-    double bytes = 0.0;
-    for (auto &l : B.L) bytes += (double)l.m * (double)l.ld * (double)l.es * 5.0;
-    const double t_pass = bytes / 5e12 + 6e-6;
-    int s = (int)(2e-3 / t_pass);
-    return std::max(16, std::min(512, s));
-}
+// ------------------------------------------------------------------ arena allocator
 
-ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot_result *res,
-                    void *workspace, size_t ws_bytes, hipStream_t user_stream)
-{
-    const auto t0 = std::chrono::steady_clock::now();
-    if (count < 1 || !probs) return fail(OT_ERR_INVALID, "no problems");
-    if (!(prm.tol > 0.0)) return fail(OT_ERR_INVALID, "tol must be > 0");
-    if (prm.max_iters < 0 || prm.max_passes < 0) return fail(OT_ERR_INVALID, "negative limits");
-    Batch B;
-    ot_status st = plan_batch(probs, count, prm, B);
-    if (st != OT_OK) return st;
-
-    hipStream_t s = user_stream;
-    bool own_stream = false;
-    if (!s) {
-        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        own_stream = true;
+// First-fit allocator over byte offsets of one device allocation, 256-byte granularity,
+// coalescing free neighbours.
+class Arena {
+public:
+    void reset(size_t bytes)
+    {
+        total_ = bytes;
+        used_ = peak_ = 0;
+        free_.clear();
+        if (bytes) free_[0] = bytes;
     }
-    struct Cleanup {
-        hipStream_t s = nullptr;
-        bool own = false;
-        void *ws = nullptr;
-        std::vector<void *> tmp;
-        void *pinned = nullptr;
-        std::vector<hipEvent_t> events;
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        ~Cleanup()
-        {
-            if (s) (void)hipStreamSynchronize(s);
-            if (exec) (void)hipGraphExecDestroy(exec);
-            if (graph) (void)hipGraphDestroy(graph);
-            for (void *p : tmp) (void)hipFree(p);
-            if (ws) (void)hipFree(ws);
-            if (pinned) (void)hipHostFree(pinned);
-            for (auto e : events) (void)hipEventDestroy(e);
-            if (own && s) (void)hipStreamDestroy(s);
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1));
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
         }
-    } cl;
-    cl.s = s;
-    cl.own = own_stream;
-
-    // host-side validation of the marginals (paper: f, g probability vectors, eq. ot)
-    std::vector<std::vector<double>> fh(count), gh(count);
-    std::vector<double> tols(count);
-    for (int i = 0; i < count; ++i) {
-        st = fetch_host(probs[i].f, (size_t)probs[i].m, fh[i], s);
-        if (st != OT_OK) return st;
-        st = fetch_host(probs[i].g, (size_t)probs[i].n, gh[i], s);
-        if (st != OT_OK) return st;
-        if (!finite_nonneg(fh[i]) || !finite_nonneg(gh[i]))
-            return fail(OT_ERR_INVALID, "instance " + std::to_string(i) + ": f and g must be finite and >= 0");
-        double sf = 0.0, sg = 0.0;
-        for (double v : fh[i]) sf += v;
-        for (double v : gh[i]) sg += v;
-        if (!(std::fabs(sf - sg) <= 1e-12 * std::max(sf, sg)))
-            return fail(OT_ERR_INVALID, "instance " + std::to_string(i) + ": sum f != sum g");
-        tols[i] = probs[i].tol > 0.0 ? probs[i].tol : prm.tol;
+        return false;
     }
-
-    char *ws = (char *)workspace;
-    if (ws) {
-        if (ws_bytes < B.total) return fail(OT_ERR_OOM, "workspace too small");
-        if ((uintptr_t)ws % kAlign) return fail(OT_ERR_INVALID, "workspace must be 256-byte aligned");
-    } else {
-        void *p = nullptr;
-        if (hipMalloc(&p, B.total) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(OT_ERR_OOM, "hipMalloc of " + std::to_string(B.total) + " bytes failed");
+    bool can_alloc(size_t bytes) const
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1));
+        for (auto &kv : free_)
+            if (kv.second >= bytes) return true;
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align_up(std::max<size_t>(bytes, 1));
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
         }
-        cl.ws = p;
-        ws = (char *)p;
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
     }
-    HIP_TRY(hipMemsetAsync(ws, 0, B.total, s));
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    size_t total() const { return total_; }
 
-    std::vector<Inst> insts(count);
-    for (int i = 0; i < count; ++i) {
-        const Layout &l = B.L[i];
-        const ot_problem &pb = probs[i];
-        char *b = ws + B.base[i];
-        Inst &I = insts[i];
+private:
+    size_t total_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+// ------------------------------------------------------------------ engine
+
+// Inputs of one instance held in host memory (server requests copy them at submit).
+struct HostData {
+    std::vector<double> f, g, C, x, y;
+};
+
+struct Req {
+    Layout L;
+    ot_problem prob{};       // caller's output pointers (and input pointers for direct solves)
+    double tol = 0.0;
+    size_t off = 0;          // arena offset of the instance
+    int slot = -1;           // index in the instance table
+    Inst I{};
+    std::shared_ptr<HostData> host;   // non-null for server requests
+    uint64_t ticket = 0;
+    double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
+    int64_t slots_run = 0;
+    double pass_ms = 0.0, comb_ms = 0.0;
+    bool done = false;
+    ot_result res{};
+};
+
+class Engine {
+public:
+    ~Engine() { release(); }
+
+    // Set up the stream and the arena.  ws: caller workspace (nullable).
+    ot_status init(const ot_params &prm, hipStream_t user_stream, size_t arena_bytes, void *ws,
+                   size_t ws_bytes, int max_slots)
+    {
+        prm_ = prm;
+        s_ = user_stream;
+        if (!s_) {
+            HIP_TRY(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+            own_stream_ = true;
+        }
+        if (ws) {
+            if ((uintptr_t)ws % kAlign) return fail(OT_ERR_INVALID, "workspace must be 256-byte aligned");
+            if (ws_bytes < arena_bytes) return fail(OT_ERR_OOM, "workspace too small");
+            base_ = (char *)ws;
+            arena_bytes = ws_bytes;
+        } else {
+            void *p = nullptr;
+            if (hipMalloc(&p, arena_bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(OT_ERR_OOM, "hipMalloc of " + std::to_string(arena_bytes) + " bytes failed");
+            }
+            base_ = (char *)p;
+            own_arena_ = true;
+        }
+        arena_.reset(arena_bytes);
+        max_slots_ = max_slots;
+        // instance table and counts come first in the arena
+        if (!arena_.alloc(sizeof(Inst) * (size_t)max_slots, &off_insts_) ||
+            !arena_.alloc(sizeof(int32_t) * (kMaxGroups + 1), &off_counts_))
+            return fail(OT_ERR_OOM, "arena too small for the engine tables");
+        HIP_TRY(hipHostMalloc((void **)&h_ctl_, sizeof(Ctl) * (size_t)max_slots, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&h_counts_, sizeof(int32_t) * (kMaxGroups + 1), hipHostMallocDefault));
+        for (int i = 0; i < max_slots; ++i) free_slots_.push_back(max_slots - 1 - i);
+        for (auto &e : ev_) HIP_TRY(hipEventCreate(&e));
+        return OT_OK;
+    }
+
+    bool fits(const Layout &L) const { return !free_slots_.empty() && arena_.can_alloc(L.bytes); }
+
+    // Place an instance: workspace, inputs, cost, control block.  On success the request
+    // runs from the next graph launch on.
+    ot_status admit(Req &r)
+    {
+        if (free_slots_.empty()) return fail(OT_ERR_BUSY, "no free instance slot");
+        if (!arena_.alloc(r.L.bytes, &r.off)) return fail(OT_ERR_BUSY, "arena full");
+        r.slot = free_slots_.back();
+        free_slots_.pop_back();
+        ot_status st = setup(r);
+        if (st != OT_OK) {
+            arena_.release(r.off, r.L.bytes);
+            free_slots_.push_back(r.slot);
+            return st;
+        }
+        active_.push_back(&r);
+        dirty_ = true;
+        return OT_OK;
+    }
+
+    // Launch one block of `slots` iteration slots and refresh the host mirror of the
+    // control blocks of the running instances.
+    ot_status run_block(int slots)
+    {
+        OT_TRY(sync_tables(slots));
+        if (prm_.profile) {
+            for (int k = 0; k < slots; ++k) {
+                // the pass launches carry events stamped with their own start and end; the
+                // combine is timed from the end of the last pass to its completion
+                float a = 0.f, b = 0.f;
+                for (size_t gi = 0; gi < groups_.size(); ++gi) {
+                    const Group &g = groups_[gi];
+                    HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), d_tiles() + g.first,
+                                        d_counts() + gi, g.grid, s_, ev_[0], ev_[1]));
+                    HIP_TRY(hipEventSynchronize(ev_[1]));
+                    float t = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
+                    a += t;
+                }
+                HIP_TRY(launch_combine(d_insts(), d_combs(), d_counts() + kMaxGroups, comb_grid_, s_));
+                HIP_TRY(hipEventRecord(ev_[2], s_));
+                HIP_TRY(hipEventSynchronize(ev_[2]));
+                HIP_TRY(hipEventElapsedTime(&b, ev_[1], ev_[2]));
+                for (Req *r : active_)
+                    if (h_ctl_[r->slot].mode != M_IDLE) {
+                        r->pass_ms += a;
+                        r->comb_ms += b;
+                    }
+                for (Req *r : active_)
+                    HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+                HIP_TRY(hipStreamSynchronize(s_));
+            }
+        } else {
+            HIP_TRY(hipGraphLaunch(exec_, s_));
+        }
+        for (Req *r : active_) {
+            r->slots_run += slots;
+            HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+        }
+        HIP_TRY(hipStreamSynchronize(s_));
+        ++launches_;
+        return OT_OK;
+    }
+
+    const Ctl &ctl(const Req &r) const { return h_ctl_[r.slot]; }
+
+    // Ask a running instance to stop at its next decision point (time limits).
+    ot_status request_stop(Req &r)
+    {
+        const int32_t one = 1;
+        HIP_TRY(hipMemcpyAsync((char *)r.I.ctl + offsetof(Ctl, stop), &one, sizeof(one),
+                               hipMemcpyHostToDevice, s_));
+        HIP_TRY(hipStreamSynchronize(s_));
+        h_ctl_[r.slot].stop = 1;
+        return OT_OK;
+    }
+
+    // Copy the outputs of a finished instance, fill its result and release its space.
+    ot_status retire(Req &r, ot_status forced = OT_OK)
+    {
+        const Ctl &c = h_ctl_[r.slot];
+        const Layout &l = r.L;
+        const Inst &I = r.I;
+        ot_status ist = forced != OT_OK ? forced : (c.status < 0 ? OT_ERR_DEVICE : (ot_status)c.status);
+        ot_status copy_st = OT_OK;
+        if (ist == OT_OK || ist == OT_NOT_CONVERGED) copy_st = copy_outputs(r, c);
+        ot_result &o = r.res;
+        memset(&o, 0, sizeof(o));
+        o.status = copy_st != OT_OK ? copy_st : ist;
+        o.returned_average = c.ret_avg;
+        o.iterations = c.T;
+        o.passes = c.passes;
+        o.restarts = c.restarts;
+        o.kernel_passes = c.kpasses;
+        o.objective = c.r_obj;
+        o.dual_objective = c.r_dobj;
+        o.rel_primal = c.r_relP;
+        o.rel_dual = c.r_relD;
+        o.rel_gap = c.r_relG;
+        o.rel_kkt = c.r_kkt;
+        o.eta = c.eta;
+        o.omega = c.omega;
+        // algorithmic bytes per element of each pass kind (plan element size b, cost
+        // element size bc, 0 when regenerated): start-point KKT reads C; a trial reads X
+        // and C and writes X+; the full pass also reads and writes the average; the
+        // restart pass reads two plans; verification reads X and C
+        const double b = (double)l.es, bc = l.stored ? (double)l.es : 0.0;
+        const double per[6] = {0.0, bc, 2 * b + bc, 4 * b + bc, 2 * b, b + bc};
+        const double elems = (double)l.m * (double)l.n;
+        double bytes = 0.0;
+        for (int k = 0; k < 6; ++k) {
+            o.mode_passes[k] = c.mcount[k];
+            bytes += per[k] * elems * (double)c.mcount[k];
+        }
+        o.pass_bytes = bytes;
+        o.pass_ms = r.pass_ms;
+        o.combine_ms = r.comb_ms;
+        (void)I;
+        r.done = true;
+        arena_.release(r.off, l.bytes);
+        free_slots_.push_back(r.slot);
+        active_.erase(std::remove(active_.begin(), active_.end(), &r), active_.end());
+        dirty_ = true;
+        return copy_st;
+    }
+
+    const std::vector<Req *> &active() const { return active_; }
+    size_t arena_used() const { return arena_.used(); }
+    size_t arena_peak() const { return arena_.peak(); }
+    size_t arena_total() const { return arena_.total(); }
+    int64_t launches() const { return launches_; }
+
+    // Slots per graph launch for the running set: about target_ms of streaming at
+    // roughly 5 TB/s, between 4 and 512 slots.
+    int auto_slots(double target_ms) const
+    {
+        double bytes = 0.0;
+        for (const Req *r : active_) bytes += (double)r->L.m * (double)r->L.ld * (double)r->L.es * 5.0;
+        const double t_slot = bytes / 5e12 + 8e-6;
+        int s = (int)(target_ms * 1e-3 / t_slot);
+        return std::max(4, std::min(512, s));
+    }
+
+    void release()
+    {
+        if (s_) (void)hipStreamSynchronize(s_);
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+        for (auto &e : ev_) {
+            if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+        if (h_ctl_) (void)hipHostFree(h_ctl_);
+        if (h_counts_) (void)hipHostFree(h_counts_);
+        h_ctl_ = nullptr;
+        h_counts_ = nullptr;
+        if (own_arena_ && base_) (void)hipFree(base_);
+        base_ = nullptr;
+        if (own_stream_ && s_) (void)hipStreamDestroy(s_);
+        s_ = nullptr;
+    }
+
+private:
+    struct Group {
+        int fp32, vec, cost;
+        int first, cap, grid;
+    };
+
+    Inst *d_insts() const { return (Inst *)(base_ + off_insts_); }
+    int32_t *d_counts() const { return (int32_t *)(base_ + off_counts_); }
+    Tile *d_tiles() const { return (Tile *)(base_ + off_tiles_); }
+    CombEntry *d_combs() const { return (CombEntry *)(base_ + off_combs_); }
+
+    ot_status copy_outputs(Req &r, const Ctl &c)
+    {
+        const Layout &l = r.L;
+        const Inst &I = r.I;
+        if (r.prob.X_out)
+            HIP_TRY(hipMemcpy2DAsync(r.prob.X_out, l.n * l.es, I.X[c.ret_x], l.ld * l.es, l.n * l.es, l.m,
+                                     hipMemcpyDefault, s_));
+        const double *pr = c.ret_avg ? I.pb[c.pbv] : I.p[c.pv];
+        const double *qr = c.ret_avg ? I.qb[c.pbv] : I.q[c.pv];
+        if (r.prob.u_out) HIP_TRY(hipMemcpyAsync(r.prob.u_out, pr, sizeof(double) * l.m, hipMemcpyDefault, s_));
+        if (r.prob.v_out) HIP_TRY(hipMemcpyAsync(r.prob.v_out, qr, sizeof(double) * l.n, hipMemcpyDefault, s_));
+        HIP_TRY(hipStreamSynchronize(s_));
+        return OT_OK;
+    }
+
+    ot_status setup(Req &r)
+    {
+        const Layout &l = r.L;
+        const ot_problem &pb = r.prob;
+        char *b = base_ + r.off;
+        Inst &I = r.I;
         memset(&I, 0, sizeof(I));
         I.m = l.m;
         I.n = l.n;
@@ -403,31 +639,37 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
         I.combscal = (double *)(b + l.off_comb);
         I.counter = (uint32_t *)(b + l.off_counter);
         I.ctl = (Ctl *)(b + l.off_ctl);
-        I.prm = device_params(prm, tols[i]);
+        I.prm = device_params(prm_, r.tol);
 
-        HIP_TRY(hipMemcpyAsync((void *)I.f, fh[i].data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync((void *)I.g, gh[i].data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemsetAsync(b, 0, l.bytes, s_));
+        const HostData *h = r.host.get();
+        HIP_TRY(hipMemcpyAsync((void *)I.f, h ? (const void *)h->f.data() : (const void *)pb.f,
+                               sizeof(double) * m, hipMemcpyDefault, s_));
+        HIP_TRY(hipMemcpyAsync((void *)I.g, h ? (const void *)h->g.data() : (const void *)pb.g,
+                               sizeof(double) * n, hipMemcpyDefault, s_));
         if (l.dim) {
-            HIP_TRY(hipMemcpyAsync((void *)I.xs, pb.cost.x, sizeof(double) * m * l.dim, hipMemcpyDefault, s));
-            HIP_TRY(hipMemcpyAsync((void *)I.ys, pb.cost.y, sizeof(double) * n * l.dim, hipMemcpyDefault, s));
+            HIP_TRY(hipMemcpyAsync((void *)I.xs, h ? (const void *)h->x.data() : (const void *)pb.cost.x,
+                                   sizeof(double) * m * l.dim, hipMemcpyDefault, s_));
+            HIP_TRY(hipMemcpyAsync((void *)I.ys, h ? (const void *)h->y.data() : (const void *)pb.cost.y,
+                                   sizeof(double) * n * l.dim, hipMemcpyDefault, s_));
         }
         if (l.stored) {
             int kind = C_STORED;
             const double *src = nullptr;
             int64_t ldc = 0;
+            void *tmp = nullptr;
             if (pb.cost.kind == OT_COST_DENSE) {
-                ldc = pb.cost.ldc;
-                if (is_device_ptr(pb.cost.C)) {
-                    src = pb.cost.C;
+                ldc = h ? n : pb.cost.ldc;
+                const double *C = h ? h->C.data() : pb.cost.C;
+                if (!h && is_device_ptr(C)) {
+                    src = C;
                 } else {
-                    void *tmp = nullptr;
                     const size_t bytes = sizeof(double) * (size_t)((m - 1) * ldc + n);
-                    if (hipMalloc(&tmp, bytes) != hipSuccess) {
+                    if (hipMallocAsync(&tmp, bytes, s_) != hipSuccess) {
                         (void)hipGetLastError();
                         return fail(OT_ERR_OOM, "staging allocation for C failed");
                     }
-                    cl.tmp.push_back(tmp);
-                    HIP_TRY(hipMemcpyAsync(tmp, pb.cost.C, bytes, hipMemcpyHostToDevice, s));
+                    HIP_TRY(hipMemcpyAsync(tmp, C, bytes, hipMemcpyHostToDevice, s_));
                     src = (const double *)tmp;
                 }
             } else if (pb.cost.kind == OT_COST_GRID_SQEUCLID) {
@@ -436,177 +678,400 @@ ot_status run_batch(const ot_problem *probs, int count, const ot_params &prm, ot
                 kind = pb.cost.kind == OT_COST_POINTS_SQEUCLID ? C_PTS_SQ : C_PTS_EU;
             }
             HIP_TRY(launch_materialize(l.fp32, (void *)I.C, m, n, l.ld, kind, src, ldc, I.xs, I.ys,
-                                       l.dim, l.side, pb.cost.scale, s));
+                                       l.dim, l.side, pb.cost.scale, s_));
+            if (tmp) HIP_TRY(hipFreeAsync(tmp, s_));
         }
         Ctl c;
         memset(&c, 0, sizeof(c));
         c.mode = M_INIT;
-        c.status = -1;
+        c.status = ST_RUNNING;
         for (int k = 0; k < 4; ++k) c.xr[k] = k;
-        c.eta = prm.eta0 > 0.0 ? prm.eta0 : 1.0 / std::sqrt((double)(m + n));
-        c.omega = prm.omega0 > 0.0 ? prm.omega0 : 1.0;
-        c.tol_eff = tols[i];
-        HIP_TRY(hipMemcpyAsync(I.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));   // host staging buffers above are on the stack
+        c.eta = prm_.eta0 > 0.0 ? prm_.eta0 : 1.0 / std::sqrt((double)(m + n));
+        c.omega = prm_.omega0 > 0.0 ? prm_.omega0 : 1.0;
+        c.tol_eff = r.tol;
+        h_ctl_[r.slot] = c;
+        HIP_TRY(hipMemcpyAsync(I.ctl, &h_ctl_[r.slot], sizeof(Ctl), hipMemcpyHostToDevice, s_));
+        HIP_TRY(hipMemcpyAsync(d_insts() + r.slot, &I, sizeof(Inst), hipMemcpyHostToDevice, s_));
+        // host sources above must stay alive until the copies are done
+        HIP_TRY(hipStreamSynchronize(s_));
+        return OT_OK;
     }
-    const Inst *d_insts = (const Inst *)(ws + B.inst_tab);
-    const Tile *d_tiles = (const Tile *)(ws + B.tile_tab);
-    const CombEntry *d_combs = (const CombEntry *)(ws + B.comb_tab);
-    HIP_TRY(hipMemcpyAsync((void *)d_insts, insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync((void *)d_tiles, B.tiles.data(), sizeof(Tile) * B.tiles.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync((void *)d_combs, B.combs.data(), sizeof(CombEntry) * B.combs.size(), hipMemcpyHostToDevice, s));
 
-    // one graph of `slots` iteration slots
-    const int slots = prm.graph_slots > 0 ? prm.graph_slots : auto_slots(B);
-    const int comb_grid = std::min(B.ncomb_total, kMaxGrid);
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    for (int sl = 0; sl < slots; ++sl) {
-        for (auto &g : B.groups) {
-            const int grid = std::min(g.count, kMaxGrid);
-            hipError_t e = launch_pass(g.fp32, g.vec, g.cost, d_insts, d_tiles + g.first, g.count, grid, s);
-            if (e != hipSuccess) {
-                hipGraph_t junk = nullptr;
-                (void)hipStreamEndCapture(s, &junk);
-                if (junk) (void)hipGraphDestroy(junk);
-                return fail(OT_ERR_DEVICE, std::string("pass launch: ") + hipGetErrorString(e));
+    // Rebuild the tile and combine tables of the running set; capture the graph again when
+    // the variant layout changed or the tables had to grow.
+    ot_status sync_tables(int slots)
+    {
+        if (!dirty_ && (exec_ || prm_.profile) && slots == graph_slots_) return OT_OK;
+        struct Key {
+            int fp32, vec, cost;
+        };
+        std::vector<Key> keys;
+        for (Req *r : active_) {
+            bool seen = false;
+            for (auto &k : keys) seen |= k.fp32 == r->L.fp32 && k.vec == r->L.vec && k.cost == r->L.cost;
+            if (!seen) keys.push_back({r->L.fp32, r->L.vec, r->L.cost});
+        }
+        if ((int)keys.size() > kMaxGroups) return fail(OT_ERR_INVALID, "too many kernel variants in one run");
+        std::vector<std::vector<Tile>> per(keys.size());
+        std::vector<CombEntry> combs;
+        for (Req *r : active_) {
+            const Layout &l = r->L;
+            size_t gi = 0;
+            while (!(keys[gi].fp32 == l.fp32 && keys[gi].vec == l.vec && keys[gi].cost == l.cost)) ++gi;
+            for (int rb = 0; rb < l.nrb; ++rb)
+                for (int cb = 0; cb < l.ncb; ++cb) per[gi].push_back(Tile{r->slot, rb, cb, rb * l.ncb + cb});
+            int local = 0;
+            for (int64_t i = 0; i < l.m; i += kCombEntries) combs.push_back(CombEntry{r->slot, 0, (int)i, local++});
+            for (int64_t j = 0; j < l.n; j += kCombEntries) combs.push_back(CombEntry{r->slot, 1, (int)j, local++});
+        }
+        // keep the current layout when every variant still fits its region
+        bool relayout = (!exec_ && !prm_.profile) || slots != graph_slots_ || (int64_t)combs.size() > comb_cap_;
+        std::vector<int> map(keys.size(), -1);
+        for (size_t k = 0; k < keys.size(); ++k) {
+            for (size_t g = 0; g < groups_.size(); ++g)
+                if (groups_[g].fp32 == keys[k].fp32 && groups_[g].vec == keys[k].vec &&
+                    groups_[g].cost == keys[k].cost && (int64_t)per[k].size() <= groups_[g].cap)
+                    map[k] = (int)g;
+            if (map[k] < 0) relayout = true;
+        }
+        if (relayout) {
+            std::vector<Group> ng;
+            int64_t total = 0;
+            for (size_t k = 0; k < keys.size(); ++k) {
+                // room to spare so that instances joining later rarely force a new capture
+                const int cap = (int)std::max<int64_t>(256, (int64_t)per[k].size() * 3 / 2 + 64);
+                ng.push_back(Group{keys[k].fp32, keys[k].vec, keys[k].cost, (int)total, cap,
+                                   std::min(cap, kMaxGrid)});
+                map[k] = (int)k;
+                total += cap;
             }
-        }
-        hipError_t e = launch_combine(d_insts, d_combs, B.ncomb_total, comb_grid, s);
-        if (e != hipSuccess) {
-            hipGraph_t junk = nullptr;
-            (void)hipStreamEndCapture(s, &junk);
-            if (junk) (void)hipGraphDestroy(junk);
-            return fail(OT_ERR_DEVICE, std::string("combine launch: ") + hipGetErrorString(e));
-        }
-    }
-    HIP_TRY(hipStreamEndCapture(s, &cl.graph));
-    HIP_TRY(hipGraphInstantiate(&cl.exec, cl.graph, nullptr, nullptr, 0));
-
-    HIP_TRY(hipHostMalloc(&cl.pinned, sizeof(Ctl) * count, hipHostMallocDefault));
-    Ctl *hc = (Ctl *)cl.pinned;
-    for (int i = 0; i < count; ++i) hc[i].mode = M_INIT;
-    // every slot either evaluates a step trial, restarts, or finishes; bound the launches
-    const int64_t max_slots = 3 * std::max<int64_t>(prm.max_passes, 1) + 16;
-    int64_t launched = 0;
-    bool stop_sent = false;
-    std::vector<double> pass_ms(count, 0.0), comb_ms(count, 0.0);
-    std::vector<hipEvent_t> ev;
-    if (prm.profile) {
-        ev.resize(3);
-        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
-        cl.events = ev;
-    }
-    while (true) {
-        if (prm.profile) {
-            // one slot at a time, pass and combine launches bracketed by events
-            HIP_TRY(hipEventRecord(ev[0], s));
-            for (auto &g : B.groups)
-                HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts, d_tiles + g.first, g.count,
-                                    std::min(g.count, kMaxGrid), s));
-            HIP_TRY(hipEventRecord(ev[1], s));
-            HIP_TRY(launch_combine(d_insts, d_combs, B.ncomb_total, comb_grid, s));
-            HIP_TRY(hipEventRecord(ev[2], s));
-            launched += 1;
-            HIP_TRY(hipEventSynchronize(ev[2]));
-            float a = 0.f, b = 0.f;
-            HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
-            HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
-            // attribute to every instance still running (single instance in practice)
-            for (int i = 0; i < count; ++i)
-                if (hc[i].mode != M_IDLE) {
-                    pass_ms[i] += a;
-                    comb_ms[i] += b;
-                }
-        } else {
-            HIP_TRY(hipGraphLaunch(cl.exec, s));
-            launched += slots;
-        }
-        for (int i = 0; i < count; ++i)
-            HIP_TRY(hipMemcpyAsync(hc + i, insts[i].ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        bool running = false;
-        for (int i = 0; i < count; ++i) running |= hc[i].mode != M_IDLE;
-        if (!running) break;
-        if (launched > max_slots) return fail(OT_ERR_DEVICE, "solver did not reach a final state");
-        if (!stop_sent && prm.time_limit_s > 0.0) {
-            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (el >= prm.time_limit_s) {
-                const int32_t one = 1;
-                for (int i = 0; i < count; ++i)
-                    HIP_TRY(hipMemcpyAsync((char *)insts[i].ctl + offsetof(Ctl, stop), &one, sizeof(one),
-                                           hipMemcpyHostToDevice, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                stop_sent = true;
+            const int64_t ccap = std::max<int64_t>(256, (int64_t)combs.size() * 3 / 2 + 64);
+            if (total > tile_cap_) {
+                if (tile_cap_) arena_.release(off_tiles_, sizeof(Tile) * (size_t)tile_cap_);
+                tile_cap_ = 0;
+                if (!arena_.alloc(sizeof(Tile) * (size_t)total, &off_tiles_))
+                    return fail(OT_ERR_OOM, "arena too small for the tile table");
+                tile_cap_ = total;
             }
+            if (ccap > comb_cap_) {
+                if (comb_cap_) arena_.release(off_combs_, sizeof(CombEntry) * (size_t)comb_cap_);
+                comb_cap_ = 0;
+                if (!arena_.alloc(sizeof(CombEntry) * (size_t)ccap, &off_combs_))
+                    return fail(OT_ERR_OOM, "arena too small for the combine table");
+                comb_cap_ = ccap;
+            }
+            groups_ = ng;
+            comb_grid_ = (int)std::min<int64_t>(comb_cap_, kMaxGrid);
         }
+        for (int g = 0; g <= kMaxGroups; ++g) h_counts_[g] = 0;
+        for (size_t k = 0; k < keys.size(); ++k) {
+            const Group &g = groups_[map[k]];
+            if (!per[k].empty())
+                HIP_TRY(hipMemcpyAsync(d_tiles() + g.first, per[k].data(), sizeof(Tile) * per[k].size(),
+                                       hipMemcpyHostToDevice, s_));
+            h_counts_[map[k]] = (int32_t)per[k].size();
+        }
+        if (!combs.empty())
+            HIP_TRY(hipMemcpyAsync(d_combs(), combs.data(), sizeof(CombEntry) * combs.size(),
+                                   hipMemcpyHostToDevice, s_));
+        h_counts_[kMaxGroups] = (int32_t)combs.size();
+        HIP_TRY(hipMemcpyAsync(d_counts(), h_counts_, sizeof(int32_t) * (kMaxGroups + 1),
+                               hipMemcpyHostToDevice, s_));
+        HIP_TRY(hipStreamSynchronize(s_));   // the host tables above are temporaries
+        dirty_ = false;
+        if (relayout && !prm_.profile) OT_TRY(capture(slots));
+        graph_slots_ = slots;
+        return OT_OK;
     }
 
-    // outputs
-    ot_status first_bad = OT_OK;
+    ot_status capture(int slots)
+    {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (graph_) (void)hipGraphDestroy(graph_);
+        exec_ = nullptr;
+        graph_ = nullptr;
+        // relaxed: other threads (callers submitting to a server) may use the runtime while
+        // this thread captures
+        HIP_TRY(hipStreamBeginCapture(s_, hipStreamCaptureModeRelaxed));
+        hipError_t e = hipSuccess;
+        for (int sl = 0; sl < slots && e == hipSuccess; ++sl) {
+            for (size_t gi = 0; gi < groups_.size() && e == hipSuccess; ++gi) {
+                const Group &g = groups_[gi];
+                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), d_tiles() + g.first, d_counts() + gi,
+                                g.grid, s_);
+            }
+            if (e == hipSuccess) e = launch_combine(d_insts(), d_combs(), d_counts() + kMaxGroups, comb_grid_, s_);
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(s_, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(OT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        graph_ = g;
+        HIP_TRY(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        return OT_OK;
+    }
+
+    ot_params prm_{};
+    hipStream_t s_ = nullptr;
+    bool own_stream_ = false, own_arena_ = false;
+    char *base_ = nullptr;
+    Arena arena_;
+    int max_slots_ = 0;
+    std::vector<int> free_slots_;
+    std::vector<Req *> active_;
+    size_t off_insts_ = 0, off_counts_ = 0, off_tiles_ = 0, off_combs_ = 0;
+    int64_t tile_cap_ = 0, comb_cap_ = 0;
+    std::vector<Group> groups_;
+    int comb_grid_ = 1;
+    bool dirty_ = true;
+    int graph_slots_ = 0;
+    Ctl *h_ctl_ = nullptr;
+    int32_t *h_counts_ = nullptr;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+    hipEvent_t ev_[3] = {nullptr, nullptr, nullptr};
+    int64_t launches_ = 0;
+};
+
+// ------------------------------------------------------------------ fixed batches
+
+struct Planned {
+    std::vector<Layout> L;
+    size_t total = 0;
+};
+
+// Arena bytes for a fixed set: the engine's instance table and counts, every instance in
+// admission order, then the tile table (one region per kernel variant, each sized as
+// sync_tables sizes it) and the combine table.
+ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, Planned &P)
+{
+    P.L.resize(count);
+    int64_t combs = 0;
+    std::vector<std::pair<std::tuple<int, int, int>, int64_t>> per;
     for (int i = 0; i < count; ++i) {
-        const Layout &l = B.L[i];
-        const ot_problem &pb = probs[i];
-        const Ctl &c = hc[i];
-        const Inst &I = insts[i];
-        const ot_status ist = c.status < 0 ? OT_ERR_DEVICE : (ot_status)c.status;
-        if (ist != OT_OK && first_bad == OT_OK) first_bad = ist;
-        if (ist == OT_OK || ist == OT_NOT_CONVERGED) {
-            if (pb.X_out)
-                HIP_TRY(hipMemcpy2DAsync(pb.X_out, l.n * l.es, I.X[c.ret_x], l.ld * l.es, l.n * l.es,
-                                         l.m, hipMemcpyDefault, s));
-            const double *pr = c.ret_avg ? I.pb[c.pbv] : I.p[c.pv];
-            const double *qr = c.ret_avg ? I.qb[c.pbv] : I.q[c.pv];
-            if (pb.u_out) HIP_TRY(hipMemcpyAsync(pb.u_out, pr, sizeof(double) * l.m, hipMemcpyDefault, s));
-            if (pb.v_out) HIP_TRY(hipMemcpyAsync(pb.v_out, qr, sizeof(double) * l.n, hipMemcpyDefault, s));
-        }
-        if (res) {
-            ot_result &r = res[i];
-            memset(&r, 0, sizeof(r));
-            r.status = ist;
-            r.returned_average = c.ret_avg;
-            r.iterations = c.T;
-            r.passes = c.passes;
-            r.restarts = c.restarts;
-            r.kernel_passes = c.kpasses;
-            r.objective = c.r_obj;
-            r.dual_objective = c.r_dobj;
-            r.rel_primal = c.r_relP;
-            r.rel_dual = c.r_relD;
-            r.rel_gap = c.r_relG;
-            r.rel_kkt = c.r_kkt;
-            r.eta = c.eta;
-            r.omega = c.omega;
-            // algorithmic bytes per element of each pass kind (plan element size b, cost
-            // element size bc, 0 when regenerated): start-point KKT reads C; a trial reads
-            // X and C and writes X+; the full pass also reads and writes the average; the
-            // restart pass reads two plans; verification reads X and C
-            const double b = (double)l.es, bc = l.stored ? (double)l.es : 0.0;
-            const double per[6] = {0.0, bc, 2 * b + bc, 4 * b + bc, 2 * b, b + bc};
-            const double elems = (double)l.m * (double)l.n;
-            double bytes = 0.0;
-            for (int k = 0; k < 6; ++k) {
-                r.mode_passes[k] = c.mcount[k];
-                bytes += per[k] * elems * (double)c.mcount[k];
+        ot_status st = plan_instance(probs[i], prm, P.L[i]);
+        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+        const Layout &l = P.L[i];
+        combs += l.ncomb;
+        auto key = std::make_tuple(l.fp32, l.vec, l.cost);
+        bool seen = false;
+        for (auto &kv : per)
+            if (kv.first == key) {
+                kv.second += l.ntiles;
+                seen = true;
             }
-            r.pass_bytes = bytes;
-            r.pass_ms = pass_ms[i];
-            r.combine_ms = comb_ms[i];
+        if (!seen) per.push_back({key, (int64_t)l.ntiles});
+    }
+    size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(int32_t) * (kMaxGroups + 1));
+    for (auto &l : P.L) total += align_up(l.bytes);
+    int64_t tcap = 0;
+    for (auto &kv : per) tcap += std::max<int64_t>(256, kv.second * 3 / 2 + 64);
+    const int64_t ccap = std::max<int64_t>(256, combs * 3 / 2 + 64);
+    total += align_up(sizeof(Tile) * (size_t)tcap) + align_up(sizeof(CombEntry) * (size_t)ccap);
+    P.total = total;
+    return OT_OK;
+}
+
+ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot_result *res,
+                    void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    const double t0 = now_s();
+    if (count < 1 || !probs) return fail(OT_ERR_INVALID, "no problems");
+    OT_TRY(check_params(prm));
+    Planned P;
+    OT_TRY(plan_fixed(probs, count, prm, P));
+    std::vector<Req> reqs(count);
+    for (int i = 0; i < count; ++i) {
+        std::vector<double> fh, gh;
+        OT_TRY(fetch_host(probs[i].f, (size_t)probs[i].m, fh));
+        OT_TRY(fetch_host(probs[i].g, (size_t)probs[i].n, gh));
+        ot_status st = validate_marginals(fh, gh);
+        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+        reqs[i].L = P.L[i];
+        reqs[i].prob = probs[i];
+        reqs[i].tol = probs[i].tol > 0.0 ? probs[i].tol : prm.tol;
+    }
+    Engine E;
+    OT_TRY(E.init(prm, stream, P.total, workspace, ws_bytes, count));
+    for (int i = 0; i < count; ++i) {
+        ot_status st = E.admit(reqs[i]);
+        if (st != OT_OK)
+            return fail(st == OT_ERR_BUSY ? OT_ERR_OOM : st, "instance " + std::to_string(i) + ": " + g_err);
+    }
+    const int slots = prm.graph_slots > 0 ? prm.graph_slots : E.auto_slots(2.0);
+    bool stop_sent = false;
+    ot_status hard = OT_OK;
+    while (!E.active().empty()) {
+        ot_status st = E.run_block(prm.profile ? 1 : slots);
+        if (st != OT_OK) return st;
+        std::vector<Req *> fin, stuck;
+        for (Req *r : E.active()) {
+            if (E.ctl(*r).mode == M_IDLE) fin.push_back(r);
+            else if (r->slots_run > 3 * std::max<int64_t>(prm.max_passes, 1) + 64) stuck.push_back(r);
+        }
+        for (Req *r : fin) {
+            r->t_done = now_s() - t0;
+            st = E.retire(*r);
+            if (st != OT_OK && hard == OT_OK) hard = st;
+        }
+        for (Req *r : stuck) {
+            r->t_done = now_s() - t0;
+            (void)E.retire(*r, OT_ERR_DEVICE);
+        }
+        if (!stop_sent && prm.time_limit_s > 0.0 && now_s() - t0 >= prm.time_limit_s) {
+            for (Req *r : E.active()) OT_TRY(E.request_stop(*r));
+            stop_sent = true;
         }
     }
-    HIP_TRY(hipStreamSynchronize(s));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (res)
-        for (int i = 0; i < count; ++i) res[i].seconds = secs;
-    if (first_bad != OT_OK) {
-        g_err = first_bad == OT_NOT_CONVERGED ? "iteration, pass or time limit reached"
-                                               : "numerical failure (NaN/Inf in KKT or step scalars)";
-    } else {
+    const double secs = now_s() - t0;
+    ot_status first_bad = hard;
+    for (int i = 0; i < count; ++i) {
+        if (reqs[i].res.status != OT_OK && first_bad == OT_OK) first_bad = (ot_status)reqs[i].res.status;
+        if (res) {
+            res[i] = reqs[i].res;
+            res[i].seconds = count == 1 ? secs : reqs[i].t_done;
+        }
+    }
+    if (first_bad == OT_OK) {
         g_err.clear();
+    } else if (first_bad == OT_NOT_CONVERGED) {
+        g_err = "iteration, pass or time limit reached";
+    } else if (first_bad == OT_ERR_NUMERIC) {
+        g_err = "numerical failure (NaN/Inf in KKT or step scalars)";
+    } else if (g_err.empty()) {
+        g_err = "solver did not reach a final state";
     }
     return first_bad;
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ server
+
+struct ot_server {
+    ot_server_cfg cfg{};
+    Engine E;
+    int device = 0;
+    double t0 = 0.0;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    bool stop = false;
+    std::deque<std::unique_ptr<Req>> queue;
+    std::vector<std::unique_ptr<Req>> running;
+    std::deque<ot_completion> done;
+    uint64_t next_ticket = 1;
+    int64_t submitted = 0, admitted = 0, completed = 0, max_running = 0, launches = 0;
+    int64_t arena_used = 0, arena_peak = 0;   // snapshots of the engine's counters
+    std::string thread_error;
+
+    // completion record of a request (called with mu held)
+    void push_done(const Req &r)
+    {
+        ot_completion c{};
+        c.ticket = r.ticket;
+        c.result = r.res;
+        c.result.seconds = r.t_done - r.t_admit;
+        c.t_submit = r.t_submit;
+        c.t_admit = r.t_admit;
+        c.t_done = r.t_done;
+        done.push_back(c);
+        ++completed;
+        cv_done.notify_all();
+    }
+
+    void loop()
+    {
+        (void)hipSetDevice(device);
+        int slots = 0;
+        while (true) {
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                if (running.empty())
+                    cv.wait(lk, [&] { return stop || !queue.empty(); });
+                if (stop) break;
+                // admit from the head of the queue while a slot and arena space are free
+                while (!queue.empty() && E.fits(queue.front()->L)) {
+                    std::unique_ptr<Req> r = std::move(queue.front());
+                    queue.pop_front();
+                    lk.unlock();
+                    r->t_admit = now_s() - t0;
+                    const ot_status st = E.admit(*r);
+                    lk.lock();
+                    if (st != OT_OK) {
+                        r->res.status = st;
+                        r->t_done = now_s() - t0;
+                        push_done(*r);
+                        continue;
+                    }
+                    ++admitted;
+                    running.push_back(std::move(r));
+                    max_running = std::max<int64_t>(max_running, (int64_t)running.size());
+                }
+                // nothing runs and the head still does not fit (tables fragment the arena):
+                // it never will, reject it
+                if (running.empty() && !queue.empty()) {
+                    std::unique_ptr<Req> r = std::move(queue.front());
+                    queue.pop_front();
+                    r->res.status = OT_ERR_OOM;
+                    r->t_admit = r->t_done = now_s() - t0;
+                    push_done(*r);
+                }
+                arena_used = (int64_t)E.arena_used();
+                arena_peak = (int64_t)E.arena_peak();
+            }
+            if (running.empty()) continue;
+            int want = cfg.params.graph_slots > 0 ? cfg.params.graph_slots
+                                                  : E.auto_slots(cfg.block_ms > 0 ? cfg.block_ms : 2.0);
+            // change the slot count only when the work changed a lot (a new slot count
+            // needs a new graph capture)
+            if (slots == 0 || want > 2 * slots || 2 * want < slots) slots = want;
+            const ot_status st = E.run_block(slots);
+            if (st != OT_OK) {
+                std::lock_guard<std::mutex> lk(mu);
+                thread_error = g_err;
+                for (auto &r : running) {
+                    r->res.status = st;
+                    r->t_done = now_s() - t0;
+                    push_done(*r);
+                }
+                running.clear();
+                cv_done.notify_all();
+                break;
+            }
+            const double tnow = now_s() - t0;
+            std::vector<Req *> fin, stuck;
+            for (auto &r : running) {
+                const Ctl &c = E.ctl(*r);
+                if (c.mode == M_IDLE) {
+                    fin.push_back(r.get());
+                } else if (r->slots_run > 3 * std::max<int64_t>(cfg.params.max_passes, 1) + 64) {
+                    stuck.push_back(r.get());
+                } else if (cfg.params.time_limit_s > 0.0 && tnow - r->t_admit >= cfg.params.time_limit_s &&
+                           !c.stop) {
+                    (void)E.request_stop(*r);
+                }
+            }
+            for (Req *r : fin) (void)E.retire(*r);
+            for (Req *r : stuck) (void)E.retire(*r, OT_ERR_DEVICE);
+            std::lock_guard<std::mutex> lk(mu);
+            launches = E.launches();
+            arena_used = (int64_t)E.arena_used();
+            arena_peak = (int64_t)E.arena_peak();
+            const double tdone = now_s() - t0;
+            for (auto &r : running)
+                if (r->done) {
+                    r->t_done = tdone;
+                    push_done(*r);
+                }
+            running.erase(std::remove_if(running.begin(), running.end(),
+                                         [](const std::unique_ptr<Req> &r) { return r->done; }),
+                          running.end());
+        }
+    }
+};
 
 extern "C" {
 
@@ -646,27 +1111,145 @@ size_t ot_workspace_size(const ot_problem *prob, const ot_params *prm)
         fail(OT_ERR_INVALID, "null argument");
         return 0;
     }
-    Batch B;
-    if (plan_batch(prob, 1, *prm, B) != OT_OK) return 0;
-    return B.total;
+    Planned P;
+    if (plan_fixed(prob, 1, *prm, P) != OT_OK) return 0;
+    return P.total;
 }
 
 ot_status ot_solve(const ot_problem *prob, const ot_params *prm, ot_result *res, void *workspace,
                    size_t workspace_bytes, void *stream)
 {
     if (!prob || !prm) return fail(OT_ERR_INVALID, "null argument");
-    return run_batch(prob, 1, *prm, res, workspace, workspace_bytes, (hipStream_t)stream);
+    return run_fixed(prob, 1, *prm, res, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 ot_status ot_solve_batch(const ot_problem *probs, int32_t count, const ot_params *prm,
                          ot_result *res, void *stream)
 {
     if (!probs || !prm || count < 1) return fail(OT_ERR_INVALID, "null argument or empty batch");
-    return run_batch(probs, count, *prm, res, nullptr, 0, (hipStream_t)stream);
+    return run_fixed(probs, count, *prm, res, nullptr, 0, (hipStream_t)stream);
+}
+
+ot_status ot_server_create(const ot_server_cfg *cfg, ot_server **out)
+{
+    if (!cfg || !out) return fail(OT_ERR_INVALID, "null argument");
+    if (cfg->max_active < 1 || cfg->hbm_budget_bytes < ((size_t)1 << 20))
+        return fail(OT_ERR_INVALID, "max_active >= 1 and a budget of at least 1 MiB are required");
+    OT_TRY(check_params(cfg->params));
+    std::unique_ptr<ot_server> s(new ot_server());
+    s->cfg = *cfg;
+    s->cfg.params.profile = 0;
+    HIP_TRY(hipGetDevice(&s->device));
+    OT_TRY(s->E.init(s->cfg.params, nullptr, cfg->hbm_budget_bytes, nullptr, 0, cfg->max_active));
+    s->t0 = now_s();
+    ot_server *raw = s.get();
+    s->th = std::thread([raw] { raw->loop(); });
+    *out = s.release();
+    g_err.clear();
+    return OT_OK;
+}
+
+ot_status ot_server_submit(ot_server *srv, const ot_problem *prob, uint64_t *ticket)
+{
+    if (!srv || !prob) return fail(OT_ERR_INVALID, "null argument");
+    std::unique_ptr<Req> r(new Req());
+    OT_TRY(plan_instance(*prob, srv->cfg.params, r->L));
+    // the instance plus its share of the engine tables must fit in the arena
+    if (r->L.bytes + ((size_t)1 << 20) > srv->E.arena_total())
+        return fail(OT_ERR_BUSY, "problem needs more device memory than the server budget");
+    auto h = std::make_shared<HostData>();
+    OT_TRY(fetch_host(prob->f, (size_t)prob->m, h->f));
+    OT_TRY(fetch_host(prob->g, (size_t)prob->n, h->g));
+    OT_TRY(validate_marginals(h->f, h->g));
+    const ot_cost &c = prob->cost;
+    if (c.kind == OT_COST_DENSE) {
+        h->C.resize((size_t)prob->m * (size_t)prob->n);
+        std::vector<double> row;
+        for (int64_t i = 0; i < prob->m; ++i) {
+            OT_TRY(fetch_host(c.C + i * c.ldc, (size_t)prob->n, row));
+            memcpy(h->C.data() + i * prob->n, row.data(), sizeof(double) * (size_t)prob->n);
+        }
+    } else if (c.kind == OT_COST_POINTS_SQEUCLID || c.kind == OT_COST_POINTS_EUCLID) {
+        OT_TRY(fetch_host(c.x, (size_t)prob->m * c.dim, h->x));
+        OT_TRY(fetch_host(c.y, (size_t)prob->n * c.dim, h->y));
+    }
+    r->host = h;
+    r->prob = *prob;
+    r->tol = prob->tol > 0.0 ? prob->tol : srv->cfg.params.tol;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (!srv->thread_error.empty()) return fail(OT_ERR_DEVICE, "server stopped: " + srv->thread_error);
+    if (srv->cfg.max_queue > 0 && (int)srv->queue.size() >= srv->cfg.max_queue)
+        return fail(OT_ERR_BUSY, "queue full");
+    r->ticket = srv->next_ticket++;
+    r->t_submit = now_s() - srv->t0;
+    if (ticket) *ticket = r->ticket;
+    srv->queue.push_back(std::move(r));
+    ++srv->submitted;
+    srv->cv.notify_all();
+    g_err.clear();
+    return OT_OK;
+}
+
+ot_status ot_server_poll(ot_server *srv, ot_completion *out, int32_t max, int32_t *n_out)
+{
+    if (!srv || (!out && max > 0) || !n_out) return fail(OT_ERR_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    int32_t k = 0;
+    while (k < max && !srv->done.empty()) {
+        out[k++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    *n_out = k;
+    return OT_OK;
+}
+
+ot_status ot_server_drain(ot_server *srv, double timeout_s)
+{
+    if (!srv) return fail(OT_ERR_INVALID, "null argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto pred = [&] { return srv->completed >= srv->submitted || !srv->thread_error.empty(); };
+    if (timeout_s > 0.0) {
+        if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred))
+            return fail(OT_NOT_CONVERGED, "drain timed out");
+    } else {
+        srv->cv_done.wait(lk, pred);
+    }
+    if (!srv->thread_error.empty()) return fail(OT_ERR_DEVICE, "server stopped: " + srv->thread_error);
+    return OT_OK;
+}
+
+ot_status ot_server_get_stats(ot_server *srv, ot_server_stats *o)
+{
+    if (!srv || !o) return fail(OT_ERR_INVALID, "null argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    o->submitted = srv->submitted;
+    o->admitted = srv->admitted;
+    o->completed = srv->completed;
+    o->running = (int64_t)srv->running.size();
+    o->queued = (int64_t)srv->queue.size();
+    o->arena_used = srv->arena_used;
+    o->arena_peak = srv->arena_peak;
+    o->launches = srv->launches;
+    o->max_running = srv->max_running;
+    return OT_OK;
+}
+
+ot_status ot_server_destroy(ot_server *srv)
+{
+    if (!srv) return fail(OT_ERR_INVALID, "null argument");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv.notify_all();
+    if (srv->th.joinable()) srv->th.join();
+    srv->E.release();
+    delete srv;
+    return OT_OK;
 }
 
 const char *ot_last_error(void) { return g_err.c_str(); }
 
-const char *ot_version(void) { return "pdot-mi355x 0.1"; }
+const char *ot_version(void) { return "pdot-mi355x 0.2"; }
 
 }  // extern "C"

@@ -35,12 +35,10 @@ def test_library_exports_every_declared_symbol():
 
 def test_ctypes_structs_match_c_layout(tmp_path):
     src = tmp_path / "layout.c"
-    fields = {
-        "ot_cost": [f for f, _ in P.OtCost._fields_],
-        "ot_problem": [f for f, _ in P.OtProblem._fields_],
-        "ot_params": [f for f, _ in P.OtParams._fields_],
-        "ot_result": [f for f, _ in P.OtResult._fields_],
-    }
+    cls = {"ot_cost": P.OtCost, "ot_problem": P.OtProblem, "ot_params": P.OtParams,
+           "ot_result": P.OtResult, "ot_server_cfg": P.OtServerCfg,
+           "ot_completion": P.OtCompletion, "ot_server_stats": P.OtServerStats}
+    fields = {st: [f for f, _ in c._fields_] for st, c in cls.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){']
     for st, fl in fields.items():
         lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
@@ -52,8 +50,6 @@ def test_ctypes_structs_match_c_layout(tmp_path):
     subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
-    cls = {"ot_cost": P.OtCost, "ot_problem": P.OtProblem, "ot_params": P.OtParams,
-           "ot_result": P.OtResult}
     for st, c in cls.items():
         assert int(got[st]) == ct.sizeof(c), st
         for f in fields[st]:
@@ -120,3 +116,12 @@ def test_workspace_size_scales_with_precision_and_cost_storage():
     regen = P.problem(P.OT_COST_POINTS_SQEUCLID, 100, 300, f, g, x=x, y=y, store=0)
     stored = P.problem(P.OT_COST_POINTS_SQEUCLID, 100, 300, f, g, x=x, y=y, store=1)
     assert P.ot_workspace_size(stored, P.params()) - P.ot_workspace_size(regen, P.params()) >= mat32
+
+
+def test_server_rejects_invalid_configuration_without_device_work():
+    st, h = P.ot_server_create(1 << 10, max_active=4)
+    assert st == P.OT_ERR_INVALID
+    st, h = P.ot_server_create(1 << 30, max_active=0)
+    assert st == P.OT_ERR_INVALID
+    st, h = P.ot_server_create(1 << 30, max_active=4, prm=P.params(tol=-1.0))
+    assert st == P.OT_ERR_INVALID
