@@ -9,8 +9,12 @@ checks).  `value` is accepted PDHG iterations per second over the timed solves.
 
 Also reported: time to 1e-4 and 1e-6, the stored-FP32-cost and plain-FP64 forms, the
 streaming kernel against the HBM roofline (durations from HIP events around every pass
-launch of one profiled solve), and the FP64 CPU oracle timed on a bounded sample.
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+launch of one profiled solve), a batch of 256 uneven instances in one ot_solve_batch
+(makespan, completion p50/p99, against solving a subset one by one), a continuous-
+batching server fed a Poisson request stream (latency p50/p99, solves/s), and the FP64
+CPU oracle timed on a bounded sample.
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-serving]
+       [--serve-requests 2000]
 """
 import argparse
 import json
@@ -90,9 +94,13 @@ def summarize_traffic(fetch_dir, write_dir, probe_log):
             vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
         copy = [v for (i, k), v in vals.items() if "copy" in k.lower() or "elementwise" in k.lower()]
         kpass = [v for (i, k), v in vals.items() if "k_pass" in k]
-        return max(copy), sum(kpass) / len(kpass), len(kpass)
+        # graph blocks also dispatch a few passes after the solve has ended, which return at
+        # once; the counts are summed over every dispatch and divided by the solver's own
+        # pass count, the denominator of the algorithmic bytes
+        return max(copy), sum(kpass) / launches, len(kpass)
 
     probe = [json.loads(x) for x in open(probe_log) if x.startswith('{"probe"')][0]
+    launches = probe["launches"]
     fc, fp, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
     wc, wp, nw = per_dispatch(write_dir, "WRITE_SIZE")
     kf, kw = COPY_BYTES / fc, COPY_BYTES / wc          # bytes per counter unit
@@ -103,8 +111,8 @@ def summarize_traffic(fetch_dir, write_dir, probe_log):
         "",
         "Counters: `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch), each in its own run:",
         "",
-        "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --traffic-probe",
-        "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --traffic-probe",
+        "    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --traffic-probe > gpurun_out/traffic_probe.log 2>&1",
+        "    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --traffic-probe > gpurun_out/traffic_probe_w.log 2>&1",
         "    python3 bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/traffic_probe.log",
         "",
         "Calibration: a plain 1 GiB device copy reads {:.0f} and writes {:.0f} counter units,".format(fc, wc),
@@ -112,12 +120,12 @@ def summarize_traffic(fetch_dir, write_dir, probe_log):
         "",
         "| quantity | per k_pass launch |",
         "|---|---|",
-        "| FETCH_SIZE (units, mean of {} dispatches) | {:.0f} |".format(nf, fp),
-        "| WRITE_SIZE (units, mean of {} dispatches) | {:.0f} |".format(nw, wp),
+        "| FETCH_SIZE (units; {} dispatches summed / {} solver passes) | {:.0f} |".format(nf, launches, fp),
+        "| WRITE_SIZE (units; {} dispatches summed / {} solver passes) | {:.0f} |".format(nw, launches, wp),
         "| read bytes (scaled) | {:.4g} |".format(fp * kf),
         "| written bytes (scaled) | {:.4g} |".format(wp * kw),
         "| traffic (read + written) | {:.4g} |".format(traffic),
-        "| algorithmic bytes (same launch mix) | {:.4g} |".format(algo),
+        "| algorithmic bytes (same launch mix: {}) | {:.4g} |".format(probe["mode_passes"], algo),
         "| traffic / algorithmic | {:.3f} |".format(traffic / algo),
         "",
         "traffic_bytes_per_launch: {:.0f}".format(traffic),
@@ -163,10 +171,156 @@ def cpu_baseline(inst, budget_s=15.0):
     t = time.perf_counter()
     _, _, _, res, _ = oracle.solve(C, inst.f, inst.g, tol=1e-12, max_iters=iters, nthreads=threads)
     dt = time.perf_counter() - t
+    if dt < 0.6 * budget_s:
+        # the first iterations ran slower than the rest: size the sample from this run
+        iters = max(2, int(iters * budget_s / dt))
+        t = time.perf_counter()
+        _, _, _, res, _ = oracle.solve(C, inst.f, inst.g, tol=1e-12, max_iters=iters,
+                                       nthreads=threads)
+        dt = time.perf_counter() - t
     del C
     return {"value": res["iterations"] / dt, "unit": "iter/s", "cores": threads, "kind": "oracle",
             "sample": f"first {res['iterations']} PDHG iterations (FP64, dense C) of the m=n=4096 "
                       f"grid instance, {dt:.1f} s on {threads} threads"}
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def problems_autotuned(P, insts, precision, kind=None):
+    """Device problems with the autotuned tile shape of each instance (plan output off)."""
+    from paper_2407_19689_amd import autotune
+    out = []
+    for inst in insts:
+        v, r = autotune.tiles_for(inst.m, inst.n, precision, kind or inst.kind)
+        pr, _ = P.problem_from_instance(inst, precision=precision, tol=inst.tol, want_plan=False,
+                                        tile_vec=v, tile_rows=r)
+        out.append(pr)
+    return out
+
+
+def batch_leg(P, count=256, seq_every=4):
+    """256 uneven Euclidean GMM instances (m, n log-uniform in [32, 2048]) solved to rel-KKT
+    1e-4 by one ot_solve_batch; a subset (every seq_every-th instance) is also solved one by
+    one with ot_solve, and as a batch of its own, for the comparison."""
+    import torch
+    from workloads import generators as gen
+    FP32 = P.OT_PREC_FP32
+    insts = gen.batch_instances(count)
+    prm = P.params(tol=1e-4, precision=FP32, time_limit_s=300.0)
+    prs = problems_autotuned(P, insts, FP32)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, res = P.ot_solve_batch(prs, prm)
+    torch.cuda.synchronize()
+    makespan = time.perf_counter() - t
+    if st != P.OT_OK:
+        raise RuntimeError(f"batch failed: {P.STATUS_NAMES.get(st)} {P.ot_last_error()}")
+    done = [r.seconds for r in res]
+    gbytes = sum(r.pass_bytes for r in res) / 1e9
+    log(f"batch: {count} instances in {makespan:.3f} s, p50 {percentile(done, 50):.3f} s, "
+        f"p99 {percentile(done, 99):.3f} s, {gbytes / makespan:.0f} GB/s algorithmic")
+    sub = list(range(0, count, seq_every))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    solo = []
+    for i in sub:
+        s1, r1 = P.ot_solve(prs[i], prm)
+        if s1 != P.OT_OK:
+            raise RuntimeError(f"solo solve {i} failed: {P.STATUS_NAMES.get(s1)}")
+        solo.append(r1)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t
+    t = time.perf_counter()
+    s2, _ = P.ot_solve_batch([prs[i] for i in sub], prm)
+    torch.cuda.synchronize()
+    sub_batch_s = time.perf_counter() - t
+    same = sum(1 for i, r1 in zip(sub, solo)
+               if r1.objective == res[i].objective and r1.iterations == res[i].iterations)
+    log(f"batch subset of {len(sub)}: sequential {seq_s:.3f} s, batched {sub_batch_s:.3f} s; "
+        f"{same}/{len(sub)} identical to the solo solves")
+    return {
+        "workload": f"{count} instances, m,n log-uniform in [32,2048] (master seed 300), 3-GMM "
+                    "points in R^3, Euclidean cost regenerated in-kernel, lognormal marginals, "
+                    "FP32 plan, rel-KKT tol 1e-4, autotuned tiles",
+        "makespan_s": round(makespan, 4), "solves_per_s": round(count / makespan, 2),
+        "completion_p50_s": round(percentile(done, 50), 4),
+        "completion_p99_s": round(percentile(done, 99), 4),
+        "aggregate_GBps": round(gbytes / makespan, 1),
+        "iterations_total": int(sum(r.iterations for r in res)),
+        "elements_total": int(sum(i.m * i.n for i in insts)),
+        "subset": {"count": len(sub), "sequential_s": round(seq_s, 4),
+                   "batched_s": round(sub_batch_s, 4),
+                   "speedup": round(seq_s / sub_batch_s, 2),
+                   "identical_to_solo": same},
+    }
+
+
+def serving_leg(P, count=200, load=0.7, sat_count=40, budget_s=90.0, iter_cap=200000):
+    """Continuous-batching server on a Poisson stream of mixed requests (points and images,
+    m, n log-uniform in [64, 16384], tol 1e-4 or 1e-6).  The saturated rate is measured by
+    submitting the first sat_count requests at once; the stream is then replayed at `load`
+    times that rate (capped to about budget_s of arrivals)."""
+    import torch
+    from workloads import generators as gen
+    FP32 = P.OT_PREC_FP32
+    stream = gen.serving_stream(count=count)
+    prm = P.params(tol=1e-4, precision=FP32, time_limit_s=120.0, max_iters=iter_cap)
+    budget = 64 << 30
+
+    def run(reqs):
+        prs = problems_autotuned(P, [x for x, _ in reqs], FP32)
+        torch.cuda.synchronize()
+        with P.Server(budget, max_active=64, prm=prm) as srv:
+            outs, t0 = {}, time.perf_counter()
+            for (inst, at), pr in zip(reqs, prs):
+                while time.perf_counter() - t0 < at:
+                    for d in srv.poll():
+                        outs[d["ticket"]] = d
+                    time.sleep(0.0005)
+                st, tk = srv.submit(pr)
+                if st != P.OT_OK:
+                    raise RuntimeError(f"submit failed: {P.STATUS_NAMES.get(st)} {P.ot_last_error()}")
+            if srv.drain(600.0) != P.OT_OK:
+                raise RuntimeError("server did not drain")
+            for d in srv.poll(4096):
+                outs[d["ticket"]] = d
+            return list(outs.values()), srv.stats()
+
+    sat = [(inst, 0.0) for _, inst in stream[:sat_count]]
+    done, _ = run(sat)
+    span = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
+    sat_rate = len(done) / span
+    rate = load * sat_rate
+    base = 10.0                         # rate the stream's arrival times were drawn at
+    use = [(inst, t * base / rate) for t, inst in stream if t * base / rate <= budget_s]
+    log(f"serving: saturated {sat_rate:.2f} solves/s on the first {sat_count}; replaying "
+        f"{len(use)} requests at {rate:.2f}/s")
+    done, stats = run(use)
+    lat = [d["t_done"] - d["t_submit"] for d in done]
+    wait = [d["t_admit"] - d["t_submit"] for d in done]
+    span = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
+    capped = sum(1 for d in done if d["status"] == P.OT_NOT_CONVERGED)
+    bad = sum(1 for d in done if d["status"] not in (P.OT_OK, P.OT_NOT_CONVERGED))
+    log(f"serving: {len(done)} done in {span:.2f} s, latency p50 {percentile(lat, 50):.3f} s "
+        f"p99 {percentile(lat, 99):.3f} s; max running {stats['max_running']}")
+    return {
+        "workload": f"Poisson stream (master seed 500), first {len(use)} of {count} requests: 90% "
+                    "point clouds in [0,1]^2 with squared-Euclidean cost, 10% blob images with "
+                    "side log-uniform in [8,128]; m,n log-uniform in [64,16384]; tol 1e-4 or "
+                    f"1e-6; FP32 plan; iteration cap {iter_cap}",
+        "requests": len(done), "rate_per_s": round(rate, 3),
+        "saturated_solves_per_s": round(sat_rate, 3), "load": load,
+        "latency_p50_s": round(percentile(lat, 50), 4),
+        "latency_p99_s": round(percentile(lat, 99), 4),
+        "queue_wait_p50_s": round(percentile(wait, 50), 4),
+        "queue_wait_p99_s": round(percentile(wait, 99), 4),
+        "solves_per_s": round(len(done) / span, 3),
+        "max_running": stats["max_running"], "arena_peak_bytes": stats["arena_peak"],
+        "graph_launches": stats["launches"], "hit_iteration_cap": capped, "failed": bad,
+    }
 
 
 def main():
@@ -177,6 +331,12 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="length of the request stream (the full stream is 2000)")
+    ap.add_argument("--serve-budget-s", type=float, default=90.0,
+                    help="replay at most this many seconds of arrivals")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the workload of the counter runs (see profiles/)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_LOG"))
@@ -252,6 +412,9 @@ def main():
                            "objective": rf["objective"], "rel_kkt": rf["rel_kkt"]}
             log(f"form {name}: {dtf:.3f} s, {rf['iterations']} iterations")
 
+    batch = None if args.no_batch else batch_leg(P)
+    serving = None if args.no_serving else serving_leg(P, count=args.serve_requests,
+                                                       budget_s=args.serve_budget_s)
     cpu = None if args.no_cpu else cpu_baseline(inst)
 
     line = {
@@ -280,6 +443,8 @@ def main():
         "rel_kkt": last["rel_kkt"],
         "roofline": roof,
         "forms": forms,
+        "batch": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -1,0 +1,39 @@
+"""Host-side logic that needs no GPU: the tile-shape cache lookup and the bench helpers."""
+import json
+
+from paper_2407_19689_amd import autotune
+
+
+def test_tiles_for_picks_the_nearest_tuned_bucket(tmp_path, monkeypatch):
+    cache = {
+        "gfx950/p1/points_euclid/5x5": {"vec": 1, "rows": 16},
+        "gfx950/p1/points_euclid/11x11": {"vec": 4, "rows": 64},
+        "gfx950/p0/points_euclid/11x11": {"vec": 2, "rows": 32},
+    }
+    f = tmp_path / "cache.json"
+    f.write_text(json.dumps(cache))
+    monkeypatch.setattr(autotune, "CACHE", str(f))
+    monkeypatch.setattr(autotune, "_cache", None)
+    assert autotune.tiles_for(40, 30, 1, "points_euclid") == (1, 16)
+    assert autotune.tiles_for(2000, 1500, 1, "points_euclid") == (4, 64)
+    assert autotune.tiles_for(2000, 1500, 0, "points_euclid") == (2, 32)
+    # nothing tuned for this kind: (0, 0) selects the library's built-in shape
+    assert autotune.tiles_for(2000, 1500, 1, "grid_sqeuclid") == (0, 0)
+
+
+def test_tiles_for_without_a_cache(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "missing.json"))
+    monkeypatch.setattr(autotune, "_cache", None)
+    assert autotune.tiles_for(100, 100, 1, "points_sqeuclid") == (0, 0)
+
+
+def test_committed_cache_holds_valid_shapes():
+    cache = autotune.load_cache()
+    for k, v in cache.items():
+        assert k.startswith("gfx950/p")
+        assert v["vec"] in (1, 2, 4) and v["rows"] >= 16 and v["rows"] % 16 == 0
+
+
+def test_bucket():
+    assert autotune.bucket(32, 2048) == (5, 11)
+    assert autotune.bucket(1, 1) == (0, 0)
