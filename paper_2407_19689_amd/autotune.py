@@ -87,8 +87,8 @@ def measure(inst, precision, vec, rows, iters):
     return (r.pass_ms + r.combine_ms) / launches
 
 
-def tune(kinds=KINDS, precision=1, quick=False, iters=60, verbose=True):
-    cache = load_cache()
+def tune(kinds=KINDS, precision=1, quick=False, iters=60, verbose=True, out=None):
+    cache = dict(load_cache())
     for kind in kinds:
         exps = list(EXPS[kind])[::2] if quick and kind != "grid_sqeuclid" else EXPS[kind]
         for em in exps:
@@ -115,7 +115,7 @@ def tune(kinds=KINDS, precision=1, quick=False, iters=60, verbose=True):
                 if verbose:
                     print(f"{kind} m={m} n={n}: vec={best[1]} rows={best[2]} "
                           f"slot {best[0] * 1e3:.1f} us", flush=True)
-    with open(CACHE, "w") as fh:
+    with open(out or CACHE, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     return cache
 
@@ -124,12 +124,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="fewer buckets and iterations")
     ap.add_argument("--kinds", default=",".join(KINDS))
+    ap.add_argument("--out", default=None, help="write the cache here instead of next to the module")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     t = time.time()
-    tune(kinds=args.kinds.split(","), quick=args.quick, iters=40 if args.quick else 60)
-    print(f"autotune done in {time.time() - t:.1f} s -> {CACHE}", flush=True)
+    tune(kinds=args.kinds.split(","), quick=args.quick, iters=40 if args.quick else 60, out=args.out)
+    print(f"autotune done in {time.time() - t:.1f} s -> {args.out or CACHE}", flush=True)
 
 
 if __name__ == "__main__":

@@ -16,8 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for the device code; the host pass prints a
-# harmless warning about the unknown target feature.
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# harmless warning about the unknown target feature.  No implicit contraction into fused
+# multiply-adds: every kernel variant that inlines the same code then rounds it alike
+# (fused multiply-adds are written out with fma() where wanted).
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
 

@@ -33,6 +33,7 @@ constexpr int kWG = 256;          // threads per work-group (4 wave64)
 constexpr int kCombEntries = 64;  // rows or columns handled by one combine work-group
 constexpr int kNS = 6;            // per-tile scalars
 constexpr int kNC = 8;            // per-combine-entry scalars
+constexpr int kNB = kNC + kNS;    // combine record: entry scalars, then its share of tile scalars
 
 // tile scalar slots
 enum { TS_DX2 = 0, TS_DRES = 1, TS_DRESB = 2, TS_POBJ = 3, TS_POBJB = 4, TS_AUX = 5 };
@@ -86,7 +87,7 @@ struct Inst {
     double *rowpart;        // [ncb][m]  row sums of each column band
     double *colpart;        // [nrb][n]  column sums of each row block
     double *tilescal;       // [ntiles][kNS]
-    double *combscal;       // [ncomb][kNC]
+    double *combscal;       // [ncomb][kNB]
     uint32_t *counter;
     Ctl *ctl;
     Prm prm;

@@ -94,17 +94,22 @@ __device__ __forceinline__ void store_pack(PDOT_GLOBAL T *__restrict__ p, const 
     *reinterpret_cast<PDOT_GLOBAL Pack<T, N> *>(p) = t;
 }
 
-// Squared distance of two points, summed over coordinates in index order with every
-// product and sum rounded separately (the same value wherever it is evaluated).
+// Squared distance of two points (dim <= 3), summed over coordinates in index order with
+// every product and sum rounded separately (the same value wherever it is evaluated).
+// The coordinate loop is unrolled with a predicate, so register arrays are indexed by
+// constants only and stay in registers.
 template <typename P1, typename P2>
 __device__ __forceinline__ double sqdist(P1 xi, P2 yj, int dim)
 {
 #pragma clang fp contract(off)
     double t = xi[0] - yj[0];
     double s = t * t;
-    for (int k = 1; k < dim; ++k) {
-        t = xi[k] - yj[k];
-        s = s + t * t;
+#pragma unroll
+    for (int k = 1; k < 3; ++k) {
+        if (k < dim) {
+            t = xi[k] - yj[k];
+            s = s + t * t;
+        }
     }
     return s;
 }
@@ -308,7 +313,9 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
             gjb[v] = (float)(int)((uint32_t)jc % (uint32_t)side);
         }
         if constexpr (kPts) {
-            for (int k = 0; k < dim; ++k) yc[v][k] = ys[jc * dim + k];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k < dim) yc[v][k] = ys[jc * dim + k];
         }
     }
 
@@ -353,7 +360,9 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
             }
             R.xi[u][0] = R.xi[u][1] = R.xi[u][2] = 0.0;
             if constexpr (kPts) {
-                for (int k = 0; k < dim; ++k) R.xi[u][k] = xs[ic * dim + k];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    if (k < dim) R.xi[u][k] = xs[ic * dim + k];
             }
 #pragma unroll
             for (int v = 0; v < VEC; ++v) R.x[u][v] = R.c[u][v] = R.b[u][v] = R.an[u][v] = (TX)0;
@@ -755,19 +764,22 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
 // ------------------------------------------------------------------ combine + control
 
 // The combine kernel: one work-group per slice of 64 rows or 64 columns of an instance.
-//  1. adds the per-tile partial sums of the slice (waves split the partials, fixed order);
+//  1. adds the per-tile partial sums of the slice (the four waves split the partials; all
+//     loads of a wave are in flight together; fixed order);
 //  2. per row/column (wave 0): KKT pieces of the current iterate and of the average, the
-//     dual step of the trial, its running average, and the step-size terms;
-//  3. hands its eight slice scalars to the last work-group of the instance (agent-scope
-//     atomic stores and a counter), which reduces them with the tile scalars of the pass
-//     in a fixed order and runs the control of Section 5 for the next slot.
+//     dual step of the trial, its running average, and the step-size terms; meanwhile
+//     wave 1 adds the scalars of the slice's share of the pass's tiles;
+//  3. hands its record (eight slice scalars, six tile scalars) to the last work-group of
+//     the instance (agent-scope atomic stores and a counter), which reduces the records in
+//     a fixed order and runs the control of Section 5 for the next slot.
 __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                                                  const CombEntry *__restrict__ ents,
                                                  const int32_t *__restrict__ count)
 {
     const int nents = *cp(count);
     __shared__ double part[4][64];
-    __shared__ double fin[4][kNC + kNS];
+    __shared__ double tsum[kNS];
+    __shared__ double fin[4][kNB];
     __shared__ int is_last;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -806,37 +818,55 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             if (mode == M_RESTART) an0 = anc[idx];
         }
 
-        // phase 1: the per-tile partial sums of this slice, in a fixed order
+        // phase 1: the per-tile partial sums of this slice, in a fixed order (wave w adds
+        // partials w, w+4, w+8, ... with up to 16 loads in flight)
         double sv = 0.0;
         if (sums) {
-            const int P4 = rows ? I.ncb : I.nrb;
-            const PDOT_GLOBAL double *src = gp(rows ? I.rowpart : I.colpart);
+            const int np = rows ? I.ncb : I.nrb;
+            const PDOT_GLOBAL double *src = gp(rows ? (const double *)I.rowpart : (const double *)I.colpart);
             if (valid) {
-                // wave w adds partials w, w+4, w+8, ...; four independent accumulators keep
-                // several loads in flight
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int pp = wave;
-                for (; pp + 12 < P4; pp += 16) {
-                    const PDOT_GLOBAL double *s0 = src + (int64_t)pp * len + idx;
-                    const int64_t st4 = (int64_t)4 * len;   // 4 partials apart
-                    a0 += s0[0];
-                    a1 += s0[st4];
-                    a2 += s0[2 * st4];
-                    a3 += s0[3 * st4];
+                for (int base = wave; base < np; base += 64) {
+                    double v[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) {
+                        const int pp = base + 4 * k;
+                        v[k] = pp < np ? src[(int64_t)pp * len + idx] : 0.0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k)
+                        if (base + 4 * k < np) sv += v[k];
                 }
-                for (; pp < P4; pp += 4) a0 += src[(int64_t)pp * len + idx];
-                sv = (a0 + a1) + (a2 + a3);
             }
             part[wave][lane] = sv;
-            __syncthreads();
-            if (wave == 0) sv = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
         }
+
+        // the tile scalars of this entry's share of the pass's tiles (wave 1)
+        if (wave == 1) {
+            const int t0 = (int)((int64_t)E.local * I.ntiles / I.ncomb);
+            const int t1 = (int)((int64_t)(E.local + 1) * I.ntiles / I.ncomb);
+            double ts[kNS];
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) ts[q] = 0.0;
+            for (int t = t0 + lane; t < t1; t += 64) {
+                const PDOT_GLOBAL double *src = gp((const double *)I.tilescal) + (int64_t)t * kNS;
+#pragma unroll
+                for (int q = 0; q < kNS; ++q) ts[q] += src[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) ts[q] = wave_sum_to63(ts[q]);
+            if (lane == 63) {
+#pragma unroll
+                for (int q = 0; q < kNS; ++q) tsum[q] = ts[q];
+            }
+        }
+        __syncthreads();
+        if (sums && wave == 0) sv = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
 
         // phase 2: per-entry vector work (wave 0, one row or column per lane)
         if (wave == 0) {
             double acc[kNC];
 #pragma unroll
-            for (int s = 0; s < kNC; ++s) acc[s] = 0.0;
+            for (int q = 0; q < kNC; ++q) acc[q] = 0.0;
             if (valid) {
                 if (mode == M_INIT) {
                     acc[CS_AUX] = fi * fi;
@@ -882,17 +912,20 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                     acc[CS_DOBJ] = fi * (st.ret_avg ? pb0 : pc0);
                 }
             }
-            // The entry scalars go to the last work-group with agent-scope atomic stores
-            // and loads, which are coherent across the chiplets' L2 caches on their own; no
+            // The record goes to the last work-group with agent-scope atomic stores and
+            // loads, which are coherent across the chiplets' L2 caches on their own; no
             // full-cache write-back or invalidation is needed for them.
             double r[kNC];
 #pragma unroll
-            for (int s = 0; s < kNC; ++s) r[s] = wave_sum_to63(acc[s]);
+            for (int q = 0; q < kNC; ++q) r[q] = wave_sum_to63(acc[q]);
             if (lane == 63) {
+                PDOT_GLOBAL double *dst = gp(I.combscal) + (int64_t)E.local * kNB;
 #pragma unroll
-                for (int s = 0; s < kNC; ++s)
-                    __hip_atomic_store(gp(I.combscal) + (int64_t)E.local * kNC + s, r[s],
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int q = 0; q < kNC; ++q)
+                    __hip_atomic_store(dst + q, r[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int q = 0; q < kNS; ++q)
+                    __hip_atomic_store(dst + kNC + q, tsum[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // those stores (same thread) complete before the counter moves
                 __builtin_amdgcn_s_waitcnt(0);
                 const unsigned prev = __hip_atomic_fetch_add(gp(I.counter), 1u, __ATOMIC_RELAXED,
@@ -903,35 +936,30 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         __syncthreads();
         if (!is_last) continue;
 
-        // phase 3 (last work-group of the instance): reduce every slice and tile scalar in
-        // a fixed order and run the control
+        // phase 3 (last work-group of the instance): reduce every record in a fixed order
+        // and run the control
         const double tt = (double)(st.T + 1);
         const double g_red = pow(tt, -P.red_exp), g_grow = pow(tt, -P.grow_exp);
-        double loc[kNC + kNS];
+        double loc[kNB];
 #pragma unroll
-        for (int s = 0; s < kNC + kNS; ++s) loc[s] = 0.0;
+        for (int q = 0; q < kNB; ++q) loc[q] = 0.0;
         for (int c = threadIdx.x; c < I.ncomb; c += kWG) {
-            const PDOT_GLOBAL double *src = gp(I.combscal) + (int64_t)c * kNC;
+            const PDOT_GLOBAL double *src = gp(I.combscal) + (int64_t)c * kNB;
 #pragma unroll
-            for (int s = 0; s < kNC; ++s)
-                loc[s] += __hip_atomic_load(src + s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        for (int t = threadIdx.x; t < I.ntiles; t += kWG) {
-            const PDOT_GLOBAL double *src = gp(I.tilescal) + (int64_t)t * kNS;
-#pragma unroll
-            for (int s = 0; s < kNS; ++s) loc[kNC + s] += src[s];
+            for (int q = 0; q < kNB; ++q)
+                loc[q] += __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
 #pragma unroll
-        for (int s = 0; s < kNC + kNS; ++s) loc[s] = wave_sum_to63(loc[s]);
+        for (int q = 0; q < kNB; ++q) loc[q] = wave_sum_to63(loc[q]);
         if (lane == 63) {
 #pragma unroll
-            for (int s = 0; s < kNC + kNS; ++s) fin[wave][s] = loc[s];
+            for (int q = 0; q < kNB; ++q) fin[wave][q] = loc[q];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            double tot[kNC + kNS];
-            for (int s = 0; s < kNC + kNS; ++s)
-                tot[s] = ((fin[0][s] + fin[1][s]) + fin[2][s]) + fin[3][s];
+            double tot[kNB];
+            for (int q = 0; q < kNB; ++q)
+                tot[q] = ((fin[0][q] + fin[1][q]) + fin[2][q]) + fin[3][q];
             Ctl c = *gp(I.ctl);
             control(c, P, mode, tot, tot + kNC, g_red, g_grow);
             *gp(I.ctl) = c;
@@ -1027,9 +1055,12 @@ hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Til
 }
 
 hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
-                          hipStream_t s)
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, insts, ents, nents);
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, ents, nents);
+    else
+        hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, insts, ents, nents);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Til
                        const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
 hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
-                          hipStream_t s);
+                          hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,
                               const double *src, int64_t ldc, const double *xs, const double *ys,
                               int dim, int side, double scale, hipStream_t s);
@@ -189,7 +189,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     L.off_rowpart = take(sizeof(double) * (size_t)L.ncb * (size_t)L.m);
     L.off_colpart = take(sizeof(double) * (size_t)L.nrb * (size_t)L.n);
     L.off_tiles = take(sizeof(double) * (size_t)L.ntiles * kNS);
-    L.off_comb = take(sizeof(double) * (size_t)L.ncomb * kNC);
+    L.off_comb = take(sizeof(double) * (size_t)L.ncomb * kNB);
     L.off_counter = take(sizeof(uint32_t) * 4);
     L.off_ctl = take(sizeof(Ctl));
     L.bytes = off;
@@ -436,8 +436,7 @@ public:
         OT_TRY(sync_tables(slots));
         if (prm_.profile) {
             for (int k = 0; k < slots; ++k) {
-                // the pass launches carry events stamped with their own start and end; the
-                // combine is timed from the end of the last pass to its completion
+                // every launch carries events stamped with its own start and end
                 float a = 0.f, b = 0.f;
                 for (size_t gi = 0; gi < groups_.size(); ++gi) {
                     const Group &g = groups_[gi];
@@ -448,10 +447,10 @@ public:
                     HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
                     a += t;
                 }
-                HIP_TRY(launch_combine(d_insts(), d_combs(), d_counts() + kMaxGroups, comb_grid_, s_));
-                HIP_TRY(hipEventRecord(ev_[2], s_));
-                HIP_TRY(hipEventSynchronize(ev_[2]));
-                HIP_TRY(hipEventElapsedTime(&b, ev_[1], ev_[2]));
+                HIP_TRY(launch_combine(d_insts(), d_combs(), d_counts() + kMaxGroups, comb_grid_, s_,
+                                       ev_[0], ev_[1]));
+                HIP_TRY(hipEventSynchronize(ev_[1]));
+                HIP_TRY(hipEventElapsedTime(&b, ev_[0], ev_[1]));
                 for (Req *r : active_)
                     if (h_ctl_[r->slot].mode != M_IDLE) {
                         r->pass_ms += a;
