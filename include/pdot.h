@@ -137,9 +137,20 @@ typedef struct {
     int32_t tile_vec;         /* columns per lane (1, 2, 4), 0 = autotuned    */
     int32_t tile_rows;        /* rows per tile (multiple of 16), 0 = autotuned */
     int32_t profile;          /* 1: launch slots one by one (no graph) and time every
-                                 streaming-pass launch with HIP events (ot_result.pass_ms) */
-    int32_t reserved;
+                                 launch with HIP events (ot_result.pass_ms, combine_ms) */
+    int32_t engine;           /* 0 auto: instances of at most OT_RESIDENT_MAX_ELEMS plan
+                                 entries run resident (one work-group runs the whole
+                                 instance for many iterations per launch), larger ones on
+                                 the whole GPU one iteration per launch; 1 always the
+                                 whole GPU; 2 resident up to OT_RESIDENT_HARD_MAX_ELEMS.
+                                 One work-group handles about one plan entry per cycle, so
+                                 the resident path only pays below a few thousand entries.
+                                 The choice depends on the instance only, so an instance
+                                 takes the same path solo, in a batch or in the server.  */
 } ot_params;
+
+#define OT_RESIDENT_MAX_ELEMS 4096
+#define OT_RESIDENT_HARD_MAX_ELEMS (1 << 22)
 
 typedef struct {
     int32_t status;            /* ot_status of this instance                       */

@@ -91,7 +91,7 @@ class OtParams(ct.Structure):
         ("tile_vec", ct.c_int32),
         ("tile_rows", ct.c_int32),
         ("profile", ct.c_int32),
-        ("reserved", ct.c_int32),
+        ("engine", ct.c_int32),
     ]
 
 

@@ -33,6 +33,13 @@
 #ifndef PDOT_RU_F64
 #define PDOT_RU_F64 2
 #endif
+// Rows each wave keeps in flight in the resident kernel (one work-group per instance has
+// few waves, so each needs more rows in flight).
+#ifndef PDOT_RU_RES
+#define PDOT_RU_RES 2
+#endif
+// Row ranges of tiles are multiples of 16 rows, so a wave may keep at most 4 rows in flight.
+static_assert(PDOT_RU_F32 <= 4 && PDOT_RU_F64 <= 4 && PDOT_RU_RES <= 4, "rows in flight exceed 16-row tiles");
 // Waves per SIMD the streaming kernel is compiled for (bounds its registers).
 #ifndef PDOT_PASS_WAVES
 #define PDOT_PASS_WAVES 2
@@ -234,6 +241,19 @@ __device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, con
     }
 }
 
+// Per-row dual of the streaming pass.  In the resident kernel the duals are rewritten by
+// other threads of the same work-group between passes, so they are read with vector
+// loads (a workgroup-scope atomic load is never turned into a scalar-cache load); in the
+// grid kernel they do not change during the launch and may come through the scalar cache.
+template <bool RES>
+__device__ __forceinline__ double row_dual(const PDOT_GLOBAL double *p, int64_t i)
+{
+    if constexpr (RES)
+        return __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        return p[i];
+}
+
 // One tile of the streaming pass.  Rows are processed RU at a time per wave (wave w takes
 // rows i0+w, i0+w+4, ...); the tile's row range is a multiple of 4*RU inside the padded
 // allocation, so every row touched exists in memory.  Padding rows (i >= m) use p_i = -inf
@@ -241,13 +261,13 @@ __device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, con
 // is 0 and no residual term is positive, so padding contributes exactly zero without a
 // masked code path.  Plan padding is zero and stays zero.  Per-row quantities (row base,
 // duals, pixel coordinates, hash) are wave-uniform and live in scalar registers.
-template <typename TX, int VEC, int COST, int MODE>
+template <typename TX, int VEC, int COST, int MODE, bool RES = false>
 __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &tl, double *lds)
 {
     // Every product and sum below is rounded as written (fused multiply-adds only where
     // fma() is spelled out), so all kernel variants (cost source, tile shape) round alike.
 #pragma clang fp contract(off)
-    constexpr int RU = sizeof(TX) == 4 ? PDOT_RU_F32 : PDOT_RU_F64;   // rows in flight per wave
+    constexpr int RU = RES ? PDOT_RU_RES : (sizeof(TX) == 4 ? PDOT_RU_F32 : PDOT_RU_F64);   // rows in flight per wave
     constexpr bool kX = MODE != M_INIT;         // reads the plan
     constexpr bool kCost = MODE != M_RESTART;   // needs C
     constexpr bool kTrial = MODE == M_TRIAL || MODE == M_FULL;
@@ -347,8 +367,8 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
             const bool rok = i < m;
             const int64_t ic = rok ? i : m - 1;
             const int64_t rowoff = i * ld + jband;   // uniform row base; lanes add jl
-            R.pi[u] = rok ? pc[i] : kNegInf;
-            R.pbi[u] = (rok && kFold) ? pbc[i] : kNegInf;
+            R.pi[u] = rok ? row_dual<RES>(pc, i) : kNegInf;
+            R.pbi[u] = (rok && kFold) ? row_dual<RES>(pbc, i) : kNegInf;
             R.gia[u] = (float)ga;
             R.gib[u] = (float)gb;
             if constexpr (kGrid) {
@@ -763,12 +783,87 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
 
 // ------------------------------------------------------------------ combine + control
 
+// Inputs of the work on one row (rows) or one column, loaded before its partial sums so
+// that both sets of loads are in flight together.
+struct IndexIn {
+    double fi, pc0, pb0, rc0, sb0, an0;
+};
+
+__device__ __forceinline__ IndexIn index_load(const PDOT_CONST Inst &I, const Ctl &st, int mode, bool rows,
+                                              int64_t idx)
+{
+    IndexIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    in.fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
+    if (mode == M_INIT) return in;
+    in.pc0 = gp(rows ? I.p[st.pv] : I.q[st.pv])[idx];
+    in.pb0 = gp(rows ? I.pb[st.pbv] : I.qb[st.pbv])[idx];
+    in.rc0 = gp(rows ? I.rs[st.rsv] : I.cs[st.rsv])[idx];
+    if (mode == M_FULL || mode == M_RESTART) in.sb0 = gp(rows ? I.rsb : I.csb)[idx];
+    if (mode == M_RESTART) in.an0 = gp(rows ? I.pa : I.qa)[idx];
+    return in;
+}
+
+// Work on one row (rows) or one column once its sums of the pass are complete (sv; 0 for
+// modes that need none): KKT pieces of the current iterate and of the average, the dual
+// step of the trial (Algorithm 2, with the extrapolated sums) and its running average,
+// the step-size terms (Section 5), the move of the duals to the restart candidate, or the
+// verified KKT pieces.  Adds the index's scalar pieces to acc.
+__device__ __forceinline__ void index_work(const PDOT_CONST Inst &I, const Ctl &st, int mode, bool rows,
+                                           int64_t idx, const IndexIn &in, double sv, double (&acc)[kNC])
+{
+    const double fi = in.fi, pc0 = in.pc0, pb0 = in.pb0, rc0 = in.rc0;
+    if (mode == M_INIT) {
+        acc[CS_AUX] += fi * fi;
+        return;
+    }
+    if (mode == M_TRIAL || mode == M_FULL) {
+        if (mode == M_FULL) {
+            // KKT of the current iterate: its sums were kept when it was accepted
+            double dl = rc0 - fi;
+            acc[CS_PRES] += dl * dl;
+            acc[CS_DOBJ] += fi * pc0;
+            // averaged sums (linear in the plan), same weights as the plan average
+            const double nb = (st.k == 1) ? rc0 : (1.0 - st.a_fold) * in.sb0 + st.a_fold * rc0;
+            gp(rows ? I.rsb : I.csb)[idx] = nb;
+            dl = nb - fi;
+            acc[CS_PRESB] += dl * dl;
+            acc[CS_DOBJB] += fi * pb0;
+        }
+        // dual step with the extrapolated sums: (2X+ - X) 1 = 2 X+ 1 - X 1, where X 1 (the
+        // current iterate's sums) was kept when X was accepted; the trial's change of the
+        // sums is X+ 1 - X 1
+        const double sigma = st.eta * st.omega;
+        const double sd = sv - rc0;
+        const double er = sv + sd;
+        const double pn = pc0 + sigma * (fi - er);
+        const double d = pn - pc0;
+        gp(rows ? I.p[st.pv ^ 1] : I.q[st.pv ^ 1])[idx] = pn;
+        gp(rows ? I.rs[st.rsv ^ 1] : I.cs[st.rsv ^ 1])[idx] = sv;
+        acc[CS_DY2] += d * d;
+        acc[CS_INTER] += d * sd;
+        // tentative running average of the duals for the trial
+        const double w = I.prm.avg_weighting == 1 ? 1.0 : st.eta;
+        const double a2 = w / (st.wsum + w);
+        gp(rows ? I.pb[st.pbv ^ 1] : I.qb[st.pbv ^ 1])[idx] = (st.k == 0) ? pn : (1.0 - a2) * pb0 + a2 * pn;
+    } else if (mode == M_RESTART) {
+        const double pnew = st.cand_avg ? pb0 : pc0;
+        const double dd = pnew - in.an0;
+        acc[CS_AUX] += dd * dd;
+        gp(rows ? I.p[st.pv] : I.q[st.pv])[idx] = pnew;
+        gp(rows ? I.pa : I.qa)[idx] = pnew;
+        if (st.cand_avg) gp(rows ? I.rs[st.rsv] : I.cs[st.rsv])[idx] = in.sb0;
+    } else if (mode == M_VERIFY) {
+        const double dl = sv - fi;
+        acc[CS_PRES] += dl * dl;
+        acc[CS_DOBJ] += fi * (st.ret_avg ? pb0 : pc0);
+    }
+}
+
 // The combine kernel: one work-group per slice of 64 rows or 64 columns of an instance.
 //  1. adds the per-tile partial sums of the slice (the four waves split the partials; all
 //     loads of a wave are in flight together; fixed order);
-//  2. per row/column (wave 0): KKT pieces of the current iterate and of the average, the
-//     dual step of the trial, its running average, and the step-size terms; meanwhile
-//     wave 1 adds the scalars of the slice's share of the pass's tiles;
+//  2. per row/column (wave 0): the index work above; meanwhile wave 1 adds the scalars of
+//     the slice's share of the pass's tiles;
 //  3. hands its record (eight slice scalars, six tile scalars) to the last work-group of
 //     the instance (agent-scope atomic stores and a counter), which reduces the records in
 //     a fixed order and runs the control of Section 5 for the next slot.
@@ -790,7 +885,6 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         const Ctl st = *gp(I.ctl);
         const int mode = st.mode;
         if (mode == M_IDLE) continue;
-        const Prm P = I.prm;
 
         const bool rows = E.kind == 0;
         const int64_t len = rows ? I.m : I.n;
@@ -798,25 +892,9 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         const bool valid = idx < len;
         const bool sums = mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY;
 
-        PDOT_GLOBAL double *pcur = gp(rows ? I.p[st.pv] : I.q[st.pv]);
-        PDOT_GLOBAL double *pnext = gp(rows ? I.p[st.pv ^ 1] : I.q[st.pv ^ 1]);
-        PDOT_GLOBAL double *pbcur = gp(rows ? I.pb[st.pbv] : I.qb[st.pbv]);
-        PDOT_GLOBAL double *pbnext = gp(rows ? I.pb[st.pbv ^ 1] : I.qb[st.pbv ^ 1]);
-        PDOT_GLOBAL double *rscur = gp(rows ? I.rs[st.rsv] : I.cs[st.rsv]);
-        PDOT_GLOBAL double *rsnext = gp(rows ? I.rs[st.rsv ^ 1] : I.cs[st.rsv ^ 1]);
-        PDOT_GLOBAL double *sbar = gp(rows ? I.rsb : I.csb);
-        PDOT_GLOBAL double *anc = gp(rows ? I.pa : I.qa);
-
         // wave 0 loads its per-entry vectors first; they do not depend on the partials
-        double fi = 0.0, pc0 = 0.0, pb0 = 0.0, rc0 = 0.0, sb0 = 0.0, an0 = 0.0;
-        if (wave == 0 && valid) {
-            fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
-            pc0 = pcur[idx];
-            pb0 = pbcur[idx];
-            rc0 = rscur[idx];
-            if (mode == M_FULL || mode == M_RESTART) sb0 = sbar[idx];
-            if (mode == M_RESTART) an0 = anc[idx];
-        }
+        IndexIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (wave == 0 && valid) in = index_load(I, st, mode, rows, idx);
 
         // phase 1: the per-tile partial sums of this slice, in a fixed order (wave w adds
         // partials w, w+4, w+8, ... with up to 16 loads in flight)
@@ -867,51 +945,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             double acc[kNC];
 #pragma unroll
             for (int q = 0; q < kNC; ++q) acc[q] = 0.0;
-            if (valid) {
-                if (mode == M_INIT) {
-                    acc[CS_AUX] = fi * fi;
-                } else if (mode == M_TRIAL || mode == M_FULL) {
-                    if (mode == M_FULL) {
-                        // KKT of the current iterate: its sums were kept when it was accepted
-                        double dl = rc0 - fi;
-                        acc[CS_PRES] = dl * dl;
-                        acc[CS_DOBJ] = fi * pc0;
-                        // averaged sums (linear in the plan), same weights as the plan average
-                        const double nb = (st.k == 1) ? rc0 : (1.0 - st.a_fold) * sb0 + st.a_fold * rc0;
-                        sbar[idx] = nb;
-                        dl = nb - fi;
-                        acc[CS_PRESB] = dl * dl;
-                        acc[CS_DOBJB] = fi * pb0;
-                    }
-                    // dual step with the extrapolated sums: (2X+ - X) 1 = 2 X+ 1 - X 1, where
-                    // X 1 (the current iterate's sums) was kept when X was accepted; the
-                    // trial's change of the sums is X+ 1 - X 1
-                    const double sigma = st.eta * st.omega;
-                    const double sd = sv - rc0;
-                    const double er = sv + sd;
-                    const double pn = pc0 + sigma * (fi - er);
-                    const double d = pn - pc0;
-                    pnext[idx] = pn;
-                    rsnext[idx] = sv;
-                    acc[CS_DY2] = d * d;
-                    acc[CS_INTER] = d * sd;
-                    // tentative running average of the duals for the trial
-                    const double w = P.avg_weighting == 1 ? 1.0 : st.eta;
-                    const double a2 = w / (st.wsum + w);
-                    pbnext[idx] = (st.k == 0) ? pn : (1.0 - a2) * pb0 + a2 * pn;
-                } else if (mode == M_RESTART) {
-                    const double pnew = st.cand_avg ? pb0 : pc0;
-                    const double dd = pnew - an0;
-                    acc[CS_AUX] = dd * dd;
-                    pcur[idx] = pnew;
-                    anc[idx] = pnew;
-                    if (st.cand_avg) rscur[idx] = sb0;
-                } else if (mode == M_VERIFY) {
-                    const double dl = sv - fi;
-                    acc[CS_PRES] = dl * dl;
-                    acc[CS_DOBJ] = fi * (st.ret_avg ? pb0 : pc0);
-                }
-            }
+            if (valid) index_work(I, st, mode, rows, idx, in, sv, acc);
             // The record goes to the last work-group with agent-scope atomic stores and
             // loads, which are coherent across the chiplets' L2 caches on their own; no
             // full-cache write-back or invalidation is needed for them.
@@ -938,6 +972,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 
         // phase 3 (last work-group of the instance): reduce every record in a fixed order
         // and run the control
+        const Prm P = I.prm;
         const double tt = (double)(st.T + 1);
         const double g_red = pow(tt, -P.red_exp), g_grow = pow(tt, -P.grow_exp);
         double loc[kNB];
@@ -965,6 +1000,110 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             *gp(I.ctl) = c;
             __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ resident instances
+
+// One work-group runs a whole instance for up to `budget` slots per launch: it streams
+// every column band of the plan itself (the tile body with all rows in one row block),
+// so the row and column sums of a pass are complete inside the work-group, then does the
+// index work of every row and column, reduces the scalars in a fixed order and runs the
+// control, with work-group barriers in place of the grid-wide kernel boundaries.  Meant
+// for small instances, whose passes are too short to fill the GPU: many of them run side
+// by side, one per work-group, without a launch per iteration.  The control block lives
+// in LDS during the launch.  Every value exchanged between threads goes through vector
+// memory operations and the barriers' workgroup-scope fences.
+template <typename TX, int VEC, int COST>
+__device__ void resident_pass(const PDOT_CONST Inst &I, const Ctl &st, int slot, double *lds)
+{
+    for (int cb = 0; cb < I.ncb; ++cb) {
+        const Tile tl{slot, 0, cb, cb};
+        switch (st.mode) {
+        case M_INIT: tile_body<TX, VEC, COST, M_INIT, true>(I, st, tl, lds); break;
+        case M_TRIAL: tile_body<TX, VEC, COST, M_TRIAL, true>(I, st, tl, lds); break;
+        case M_FULL: tile_body<TX, VEC, COST, M_FULL, true>(I, st, tl, lds); break;
+        case M_RESTART: tile_body<TX, VEC, COST, M_RESTART, true>(I, st, tl, lds); break;
+        case M_VERIFY: tile_body<TX, VEC, COST, M_VERIFY, true>(I, st, tl, lds); break;
+        default: break;
+        }
+    }
+}
+
+template <typename TX, int VEC, int COST>
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PDOT_PASS_WAVES)))
+void k_resident(const Inst *__restrict__ insts, const int32_t *__restrict__ list,
+                const int32_t *__restrict__ count, int32_t budget)
+{
+    const int nres = *cp(count);
+    __shared__ double lds[3 * 2 * 4 * 64 + 4 * kNS];
+    __shared__ double red[4][kNB];
+    __shared__ Ctl sctl;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    for (int w = blockIdx.x; w < nres; w += gridDim.x) {
+        const int slot = cp(list)[w];
+        const PDOT_CONST Inst &I = cp(insts)[slot];
+        if (threadIdx.x == 0) sctl = *gp(I.ctl);
+        __syncthreads();
+        for (int it = 0; it < budget; ++it) {
+            const Ctl st = sctl;
+            const int mode = st.mode;
+            if (mode == M_IDLE) break;
+            resident_pass<TX, VEC, COST>(I, st, slot, lds);
+            __syncthreads();
+
+            // index work over all rows, then all columns; the tile scalars of the pass
+            const bool sums = mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY;
+            double acc[kNC], ts[kNS];
+#pragma unroll
+            for (int q = 0; q < kNC; ++q) acc[q] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) ts[q] = 0.0;
+            for (int t = threadIdx.x; t < I.ncb; t += kWG) {
+                const PDOT_GLOBAL double *src = gp((const double *)I.tilescal) + (int64_t)t * kNS;
+#pragma unroll
+                for (int q = 0; q < kNS; ++q) ts[q] += src[q];
+            }
+            for (int64_t i = threadIdx.x; i < I.m; i += kWG) {
+                const IndexIn in = index_load(I, st, mode, true, i);
+                double sv = 0.0;
+                if (sums) {
+                    const PDOT_GLOBAL double *src = gp((const double *)I.rowpart) + i;
+                    for (int c = 0; c < I.ncb; ++c) sv += src[(int64_t)c * I.m];
+                }
+                index_work(I, st, mode, true, i, in, sv, acc);
+            }
+            for (int64_t j = threadIdx.x; j < I.n; j += kWG) {
+                const IndexIn in = index_load(I, st, mode, false, j);
+                const double sv = sums ? gp((const double *)I.colpart)[j] : 0.0;
+                index_work(I, st, mode, false, j, in, sv, acc);
+            }
+            double r[kNB];
+#pragma unroll
+            for (int q = 0; q < kNC; ++q) r[q] = wave_sum_to63(acc[q]);
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) r[kNC + q] = wave_sum_to63(ts[q]);
+            if (lane == 63) {
+#pragma unroll
+                for (int q = 0; q < kNB; ++q) red[wave][q] = r[q];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const Prm P = I.prm;
+                const double tt = (double)(st.T + 1);
+                double tot[kNB];
+                for (int q = 0; q < kNB; ++q)
+                    tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+                Ctl c = sctl;
+                control(c, P, mode, tot, tot + kNC, pow(tt, -P.red_exp), pow(tt, -P.grow_exp));
+                sctl = c;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *gp(I.ctl) = sctl;
         __syncthreads();
     }
 }
@@ -1062,6 +1201,52 @@ hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_
     else
         hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, insts, ents, nents);
     return hipGetLastError();
+}
+
+template <typename K>
+static hipError_t launch_r(K kernel, int grid, const Inst *insts, const int32_t *list,
+                           const int32_t *count, int32_t budget, hipStream_t s, hipEvent_t ev0,
+                           hipEvent_t ev1)
+{
+    if (ev0 && ev1)
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, list, count, budget);
+    else
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, insts, list, count, budget);
+    return hipGetLastError();
+}
+
+template <typename TX, int VEC>
+static hipError_t launch_resident_vec(int cost, const Inst *insts, const int32_t *list,
+                                      const int32_t *count, int grid, int32_t budget, hipStream_t s,
+                                      hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (cost) {
+    case C_STORED: return launch_r(k_resident<TX, VEC, C_STORED>, grid, insts, list, count, budget, s, ev0, ev1);
+    case C_PTS_SQ: return launch_r(k_resident<TX, VEC, C_PTS_SQ>, grid, insts, list, count, budget, s, ev0, ev1);
+    case C_PTS_EU: return launch_r(k_resident<TX, VEC, C_PTS_EU>, grid, insts, list, count, budget, s, ev0, ev1);
+    case C_GRID_SQ: return launch_r(k_resident<TX, VEC, C_GRID_SQ>, grid, insts, list, count, budget, s, ev0, ev1);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename TX>
+static hipError_t launch_resident_t(int vec, int cost, const Inst *insts, const int32_t *list,
+                                    const int32_t *count, int grid, int32_t budget, hipStream_t s,
+                                    hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (vec) {
+    case 1: return launch_resident_vec<TX, 1>(cost, insts, list, count, grid, budget, s, ev0, ev1);
+    case 2: return launch_resident_vec<TX, 2>(cost, insts, list, count, grid, budget, s, ev0, ev1);
+    default: return hipErrorInvalidValue;   // resident instances use 1 or 2 columns per lane
+    }
+}
+
+hipError_t launch_resident(int fp32, int vec, int cost, const Inst *insts, const int32_t *list,
+                           const int32_t *count, int grid, int32_t budget, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1)
+{
+    return fp32 ? launch_resident_t<float>(vec, cost, insts, list, count, grid, budget, s, ev0, ev1)
+                : launch_resident_t<double>(vec, cost, insts, list, count, grid, budget, s, ev0, ev1);
 }
 
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,

@@ -38,6 +38,9 @@ hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Til
                        hipEvent_t ev1 = nullptr);
 hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
                           hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_resident(int fp32, int vec, int cost, const Inst *insts, const int32_t *list,
+                           const int32_t *count, int grid, int32_t budget, hipStream_t s,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,
                               const double *src, int64_t ldc, const double *xs, const double *ys,
                               int dim, int side, double scale, hipStream_t s);
@@ -71,6 +74,8 @@ ot_status fail(ot_status st, const std::string &msg)
 constexpr size_t kAlign = 256;
 constexpr int kMaxGrid = 4096;
 constexpr int kMaxGroups = 24;   // precisions x columns-per-lane x cost sources
+// device counts: tiles per grid variant, combine entries, instances per resident variant
+constexpr int kNumCounts = 2 * kMaxGroups + 1;
 
 enum { ST_RUNNING = -1 };
 
@@ -88,6 +93,7 @@ struct Layout {
     int fp32 = 1, vec = 4, rows = 64, ncb = 0, nrb = 0, ntiles = 0, ncomb = 0;
     int cost = C_STORED, dim = 0, side = 0;
     bool stored = true;
+    bool resident = false;    // one work-group runs the whole instance
     size_t es = 4;
     size_t off_X[4] = {0, 0, 0, 0}, off_C = 0, off_xs = 0, off_ys = 0, off_f = 0, off_g = 0;
     size_t off_rowv = 0, off_colv = 0, off_rowpart = 0, off_colpart = 0;
@@ -160,11 +166,19 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     default:
         return fail(OT_ERR_INVALID, "unknown cost kind");
     }
+    if (prm.engine < 0 || prm.engine > 2) return fail(OT_ERR_INVALID, "engine must be 0, 1 or 2");
+    const int64_t elems = pb.m * pb.n;
+    L.resident = (prm.engine == 0 && elems <= OT_RESIDENT_MAX_ELEMS) ||
+                 (prm.engine == 2 && elems <= OT_RESIDENT_HARD_MAX_ELEMS);
     L.vec = pb.tile_vec > 0 ? pb.tile_vec : (prm.tile_vec ? prm.tile_vec : default_vec(pb.n));
     if (L.vec != 1 && L.vec != 2 && L.vec != 4) return fail(OT_ERR_INVALID, "tile_vec must be 1, 2 or 4");
+    // the resident kernel has no 4-column variant (it would spill registers)
+    if (L.resident && L.vec == 4) L.vec = 2;
     L.ncb = (int)((pb.n + 64 * L.vec - 1) / (64 * L.vec));
     L.rows = pb.tile_rows > 0 ? pb.tile_rows : (prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb));
     if (L.rows < 16 || L.rows % 16) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 16");
+    // a resident instance is one row block: its work-group streams every row of a band
+    if (L.resident) L.rows = (int)L.m_alloc;
     L.nrb = (int)((pb.m + L.rows - 1) / L.rows);
     const int64_t nt = (int64_t)L.ncb * L.nrb;
     if (nt > (1 << 30)) return fail(OT_ERR_INVALID, "too many tiles");
@@ -399,10 +413,12 @@ public:
         max_slots_ = max_slots;
         // instance table and counts come first in the arena
         if (!arena_.alloc(sizeof(Inst) * (size_t)max_slots, &off_insts_) ||
-            !arena_.alloc(sizeof(int32_t) * (kMaxGroups + 1), &off_counts_))
+            !arena_.alloc(sizeof(int32_t) * kNumCounts, &off_counts_))
             return fail(OT_ERR_OOM, "arena too small for the engine tables");
         HIP_TRY(hipHostMalloc((void **)&h_ctl_, sizeof(Ctl) * (size_t)max_slots, hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&h_counts_, sizeof(int32_t) * (kMaxGroups + 1), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&h_counts_, sizeof(int32_t) * kNumCounts, hipHostMallocDefault));
+        // resident instances run on a second stream, beside the graph of the others
+        HIP_TRY(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
         for (int i = 0; i < max_slots; ++i) free_slots_.push_back(max_slots - 1 - i);
         for (auto &e : ev_) HIP_TRY(hipEventCreate(&e));
         return OT_OK;
@@ -429,14 +445,28 @@ public:
         return OT_OK;
     }
 
-    // Launch one block of `slots` iteration slots and refresh the host mirror of the
-    // control blocks of the running instances.
+    // Launch one block: `slots` iteration slots of the instances that run on the whole
+    // GPU (one graph launch) and, beside them on a second stream, up to `budget` slots of
+    // every resident instance (one launch per resident variant); then refresh the host
+    // mirror of the control blocks of the running instances.
     ot_status run_block(int slots)
     {
         OT_TRY(sync_tables(slots));
+        const int budget = resident_budget(2.0);
         if (prm_.profile) {
-            for (int k = 0; k < slots; ++k) {
-                // every launch carries events stamped with its own start and end
+            // one variant at a time, every launch timed by events it stamps itself
+            for (size_t gi = 0; gi < rgroups_.size(); ++gi) {
+                const RGroup &g = rgroups_[gi];
+                HIP_TRY(launch_resident(g.fp32, g.vec, g.cost, d_insts(), d_rlist() + g.first,
+                                        d_counts() + kMaxGroups + 1 + gi, g.cap, budget, s_, ev_[0], ev_[1]));
+                HIP_TRY(hipEventSynchronize(ev_[1]));
+                float t = 0.f;
+                HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
+                for (Req *r : active_)
+                    if (r->L.resident && r->L.fp32 == g.fp32 && r->L.vec == g.vec && r->L.cost == g.cost)
+                        r->pass_ms += t;
+            }
+            for (int k = 0; k < slots && have_grid_; ++k) {
                 float a = 0.f, b = 0.f;
                 for (size_t gi = 0; gi < groups_.size(); ++gi) {
                     const Group &g = groups_[gi];
@@ -452,7 +482,7 @@ public:
                 HIP_TRY(hipEventSynchronize(ev_[1]));
                 HIP_TRY(hipEventElapsedTime(&b, ev_[0], ev_[1]));
                 for (Req *r : active_)
-                    if (h_ctl_[r->slot].mode != M_IDLE) {
+                    if (!r->L.resident && h_ctl_[r->slot].mode != M_IDLE) {
                         r->pass_ms += a;
                         r->comb_ms += b;
                     }
@@ -461,10 +491,16 @@ public:
                 HIP_TRY(hipStreamSynchronize(s_));
             }
         } else {
-            HIP_TRY(hipGraphLaunch(exec_, s_));
+            for (size_t gi = 0; gi < rgroups_.size(); ++gi) {
+                const RGroup &g = rgroups_[gi];
+                HIP_TRY(launch_resident(g.fp32, g.vec, g.cost, d_insts(), d_rlist() + g.first,
+                                        d_counts() + kMaxGroups + 1 + gi, g.cap, budget, s2_));
+            }
+            if (have_grid_) HIP_TRY(hipGraphLaunch(exec_, s_));
+            HIP_TRY(hipStreamSynchronize(s2_));
         }
         for (Req *r : active_) {
-            r->slots_run += slots;
+            r->slots_run += r->L.resident ? budget : slots;
             HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
         }
         HIP_TRY(hipStreamSynchronize(s_));
@@ -545,14 +581,30 @@ public:
     int auto_slots(double target_ms) const
     {
         double bytes = 0.0;
-        for (const Req *r : active_) bytes += (double)r->L.m * (double)r->L.ld * (double)r->L.es * 5.0;
+        for (const Req *r : active_)
+            if (!r->L.resident) bytes += (double)r->L.m * (double)r->L.ld * (double)r->L.es * 5.0;
         const double t_slot = bytes / 5e12 + 8e-6;
         int s = (int)(target_ms * 1e-3 / t_slot);
         return std::max(4, std::min(512, s));
     }
 
+    // Slots per launch for the resident instances: about target_ms for the largest of
+    // them (a work-group streams about 50 GB/s; a slot costs at least about 4 us of
+    // barriers and control), between 16 and 4096 slots.
+    int resident_budget(double target_ms) const
+    {
+        double t_slot = 0.0;
+        for (const Req *r : active_)
+            if (r->L.resident)
+                t_slot = std::max(t_slot, 4e-6 + (double)r->L.m * (double)r->L.ld * (double)r->L.es * 5.0 / 50e9);
+        if (t_slot <= 0.0) return 0;
+        const int s = (int)(target_ms * 1e-3 / t_slot);
+        return std::max(16, std::min(4096, s));
+    }
+
     void release()
     {
+        if (s2_) (void)hipStreamSynchronize(s2_);
         if (s_) (void)hipStreamSynchronize(s_);
         if (exec_) (void)hipGraphExecDestroy(exec_);
         if (graph_) (void)hipGraphDestroy(graph_);
@@ -570,6 +622,11 @@ public:
         base_ = nullptr;
         if (own_stream_ && s_) (void)hipStreamDestroy(s_);
         s_ = nullptr;
+        if (s2_) {
+            (void)hipStreamSynchronize(s2_);
+            (void)hipStreamDestroy(s2_);
+        }
+        s2_ = nullptr;
     }
 
 private:
@@ -577,11 +634,16 @@ private:
         int fp32, vec, cost;
         int first, cap, grid;
     };
+    struct RGroup {
+        int fp32, vec, cost;
+        int first, cap;   // region of the resident list; cap is also the launch grid
+    };
 
     Inst *d_insts() const { return (Inst *)(base_ + off_insts_); }
     int32_t *d_counts() const { return (int32_t *)(base_ + off_counts_); }
     Tile *d_tiles() const { return (Tile *)(base_ + off_tiles_); }
     CombEntry *d_combs() const { return (CombEntry *)(base_ + off_combs_); }
+    int32_t *d_rlist() const { return (int32_t *)(base_ + off_rlist_); }
 
     ot_status copy_outputs(Req &r, const Ctl &c)
     {
@@ -700,31 +762,66 @@ private:
     // the variant layout changed or the tables had to grow.
     ot_status sync_tables(int slots)
     {
-        if (!dirty_ && (exec_ || prm_.profile) && slots == graph_slots_) return OT_OK;
+        if (!dirty_ && (exec_ || prm_.profile || !have_grid_) && slots == graph_slots_) return OT_OK;
         struct Key {
             int fp32, vec, cost;
         };
-        std::vector<Key> keys;
-        for (Req *r : active_) {
-            bool seen = false;
-            for (auto &k : keys) seen |= k.fp32 == r->L.fp32 && k.vec == r->L.vec && k.cost == r->L.cost;
-            if (!seen) keys.push_back({r->L.fp32, r->L.vec, r->L.cost});
-        }
-        if ((int)keys.size() > kMaxGroups) return fail(OT_ERR_INVALID, "too many kernel variants in one run");
-        std::vector<std::vector<Tile>> per(keys.size());
+        std::vector<Key> keys, rkeys;
+        auto key_of = [](std::vector<Key> &ks, const Layout &l) {
+            for (size_t k = 0; k < ks.size(); ++k)
+                if (ks[k].fp32 == l.fp32 && ks[k].vec == l.vec && ks[k].cost == l.cost) return k;
+            ks.push_back({l.fp32, l.vec, l.cost});
+            return ks.size() - 1;
+        };
+        std::vector<std::vector<Tile>> per;
+        std::vector<std::vector<int32_t>> rper;
         std::vector<CombEntry> combs;
         for (Req *r : active_) {
             const Layout &l = r->L;
-            size_t gi = 0;
-            while (!(keys[gi].fp32 == l.fp32 && keys[gi].vec == l.vec && keys[gi].cost == l.cost)) ++gi;
+            if (l.resident) {
+                const size_t gi = key_of(rkeys, l);
+                if (rper.size() < rkeys.size()) rper.resize(rkeys.size());
+                rper[gi].push_back(r->slot);
+                continue;
+            }
+            const size_t gi = key_of(keys, l);
+            if (per.size() < keys.size()) per.resize(keys.size());
             for (int rb = 0; rb < l.nrb; ++rb)
                 for (int cb = 0; cb < l.ncb; ++cb) per[gi].push_back(Tile{r->slot, rb, cb, rb * l.ncb + cb});
             int local = 0;
             for (int64_t i = 0; i < l.m; i += kCombEntries) combs.push_back(CombEntry{r->slot, 0, (int)i, local++});
             for (int64_t j = 0; j < l.n; j += kCombEntries) combs.push_back(CombEntry{r->slot, 1, (int)j, local++});
         }
-        // keep the current layout when every variant still fits its region
-        bool relayout = (!exec_ && !prm_.profile) || slots != graph_slots_ || (int64_t)combs.size() > comb_cap_;
+        if ((int)keys.size() > kMaxGroups || (int)rkeys.size() > kMaxGroups)
+            return fail(OT_ERR_INVALID, "too many kernel variants in one run");
+        have_grid_ = !keys.empty();
+
+        // resident lists: one region per variant (launched directly, no graph)
+        {
+            int64_t total = 0;
+            for (auto &v : rper) total += std::max<int64_t>(64, (int64_t)v.size());
+            if (total > rlist_cap_) {
+                if (rlist_cap_) arena_.release(off_rlist_, sizeof(int32_t) * (size_t)rlist_cap_);
+                rlist_cap_ = 0;
+                const int64_t cap = total * 3 / 2 + 64;
+                if (!arena_.alloc(sizeof(int32_t) * (size_t)cap, &off_rlist_))
+                    return fail(OT_ERR_OOM, "arena too small for the resident list");
+                rlist_cap_ = cap;
+            }
+            rgroups_.clear();
+            int first = 0;
+            for (size_t k = 0; k < rkeys.size(); ++k) {
+                const int cap = (int)std::max<int64_t>(64, (int64_t)rper[k].size());
+                rgroups_.push_back(RGroup{rkeys[k].fp32, rkeys[k].vec, rkeys[k].cost, first, cap});
+                HIP_TRY(hipMemcpyAsync(d_rlist() + first, rper[k].data(), sizeof(int32_t) * rper[k].size(),
+                                       hipMemcpyHostToDevice, s_));
+                first += cap;
+            }
+        }
+
+        // grid tables: keep the current layout when every variant still fits its region
+        bool relayout = have_grid_ && ((!exec_ && !prm_.profile) || slots != graph_slots_ ||
+                                       (int64_t)combs.size() > comb_cap_);
         std::vector<int> map(keys.size(), -1);
         for (size_t k = 0; k < keys.size(); ++k) {
             for (size_t g = 0; g < groups_.size(); ++g)
@@ -762,7 +859,7 @@ private:
             groups_ = ng;
             comb_grid_ = (int)std::min<int64_t>(comb_cap_, kMaxGrid);
         }
-        for (int g = 0; g <= kMaxGroups; ++g) h_counts_[g] = 0;
+        for (int g = 0; g < kNumCounts; ++g) h_counts_[g] = 0;
         for (size_t k = 0; k < keys.size(); ++k) {
             const Group &g = groups_[map[k]];
             if (!per[k].empty())
@@ -774,8 +871,8 @@ private:
             HIP_TRY(hipMemcpyAsync(d_combs(), combs.data(), sizeof(CombEntry) * combs.size(),
                                    hipMemcpyHostToDevice, s_));
         h_counts_[kMaxGroups] = (int32_t)combs.size();
-        HIP_TRY(hipMemcpyAsync(d_counts(), h_counts_, sizeof(int32_t) * (kMaxGroups + 1),
-                               hipMemcpyHostToDevice, s_));
+        for (size_t k = 0; k < rkeys.size(); ++k) h_counts_[kMaxGroups + 1 + k] = (int32_t)rper[k].size();
+        HIP_TRY(hipMemcpyAsync(d_counts(), h_counts_, sizeof(int32_t) * kNumCounts, hipMemcpyHostToDevice, s_));
         HIP_TRY(hipStreamSynchronize(s_));   // the host tables above are temporaries
         dirty_ = false;
         if (relayout && !prm_.profile) OT_TRY(capture(slots));
@@ -820,9 +917,12 @@ private:
     int max_slots_ = 0;
     std::vector<int> free_slots_;
     std::vector<Req *> active_;
-    size_t off_insts_ = 0, off_counts_ = 0, off_tiles_ = 0, off_combs_ = 0;
-    int64_t tile_cap_ = 0, comb_cap_ = 0;
+    size_t off_insts_ = 0, off_counts_ = 0, off_tiles_ = 0, off_combs_ = 0, off_rlist_ = 0;
+    int64_t tile_cap_ = 0, comb_cap_ = 0, rlist_cap_ = 0;
     std::vector<Group> groups_;
+    std::vector<RGroup> rgroups_;
+    bool have_grid_ = false;
+    hipStream_t s2_ = nullptr;
     int comb_grid_ = 1;
     bool dirty_ = true;
     int graph_slots_ = 0;
@@ -863,12 +963,14 @@ ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, P
             }
         if (!seen) per.push_back({key, (int64_t)l.ntiles});
     }
-    size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(int32_t) * (kMaxGroups + 1));
+    size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(int32_t) * kNumCounts);
     for (auto &l : P.L) total += align_up(l.bytes);
     int64_t tcap = 0;
     for (auto &kv : per) tcap += std::max<int64_t>(256, kv.second * 3 / 2 + 64);
     const int64_t ccap = std::max<int64_t>(256, combs * 3 / 2 + 64);
     total += align_up(sizeof(Tile) * (size_t)tcap) + align_up(sizeof(CombEntry) * (size_t)ccap);
+    // resident lists, sized as sync_tables sizes them at most
+    total += align_up(sizeof(int32_t) * (size_t)(((int64_t)count + 64 * kMaxGroups) * 3 / 2 + 64));
     P.total = total;
     return OT_OK;
 }

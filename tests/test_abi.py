@@ -64,6 +64,7 @@ def test_defaults_are_the_paper_constants():
     # Section 5.1: termination tolerance and time limit
     assert p.tol == 1e-4 and p.time_limit_s == 3600.0
     assert p.precision == P.OT_PREC_FP32 and p.kkt_mode == 0 and p.restart_rule == 0
+    assert p.engine == 0          # small instances resident, large ones on the whole GPU
 
 
 def _dense(m, n):
@@ -73,7 +74,7 @@ def _dense(m, n):
 
 
 @pytest.mark.parametrize("case", ["m0", "n0", "tol", "ldc", "rows", "vec", "grid", "kind",
-                                  "dim", "prec"])
+                                  "dim", "prec", "engine"])
 def test_invalid_problems_rejected_before_device_work(case):
     f, g, C = _dense(4, 5)
     kw = {}
@@ -99,6 +100,8 @@ def test_invalid_problems_rejected_before_device_work(case):
         pr = P.problem(P.OT_COST_POINTS_SQEUCLID, 4, 5, f, g, x=x, y=np.zeros((5, 4)))
     elif case == "prec":
         kw["precision"] = 7
+    elif case == "engine":
+        kw["engine"] = 3
     st, _ = P.ot_solve(pr, P.params(**kw))
     assert st == P.OT_ERR_INVALID, (case, st, P.ot_last_error())
     assert P.ot_last_error()

@@ -76,9 +76,15 @@ SHAPES = [(37, 203, 1, 16), (37, 203, 2, 32), (37, 203, 4, 16), (1, 5, 1, 16), (
           (300, 517, 4, 64), (130, 70, 2, 48), (64, 64, 4, 16)]
 
 
+# engine 1: every slot one launch over the whole GPU; engine 2: one work-group runs the
+# whole instance (resident)
+ENGINES = [1, 2]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
 @pytest.mark.parametrize("m,n,vec,rows", SHAPES)
-def test_fixed_step_trajectory_matches_oracle(prec, m, n, vec, rows):
+def test_fixed_step_trajectory_matches_oracle(prec, m, n, vec, rows, engine):
     """Algorithm 2 with a constant step and no restart: the GPU's 30th iterate equals the
     oracle's (current iterate returned, output = 1)."""
     C, f, g = random_problem(m * 1000 + n, m, n)
@@ -86,7 +92,8 @@ def test_fixed_step_trajectory_matches_oracle(prec, m, n, vec, rows):
     common = dict(tol=1e-12, max_iters=K, step_rule=1, restart_rule=2, output=1, eta0=eta,
                   omega0=omega)
     Xo, po, qo, ro, _ = oracle.solve(C, f, g, **common)
-    st, res, X, u, v = run_dense(C, f, g, prec, tile_vec=vec, tile_rows=rows, **common)
+    st, res, X, u, v = run_dense(C, f, g, prec, tile_vec=vec, tile_rows=rows, engine=engine,
+                                 **common)
     assert st == P.OT_NOT_CONVERGED and res["iterations"] == K
     scale = np.abs(Xo).max()
     lim = 1e-13 if prec == P.OT_PREC_FP64 else 1e-6
@@ -96,8 +103,9 @@ def test_fixed_step_trajectory_matches_oracle(prec, m, n, vec, rows):
     assert np.abs(v - qo).max() <= lim * dual_scale * 10
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
-def test_average_and_candidate_match_oracle(prec):
+def test_average_and_candidate_match_oracle(prec, engine):
     """With output = 0 the returned plan is the restart candidate: the running average when
     its KKT error is not larger (Section 5).  Same candidate and same average as the
     oracle (fixed step, no restart, 25 iterations)."""
@@ -105,7 +113,7 @@ def test_average_and_candidate_match_oracle(prec):
     common = dict(tol=1e-12, max_iters=25, step_rule=1, restart_rule=2, output=0,
                   eta0=0.6 / np.sqrt(122), omega0=0.8)
     Xo, po, qo, ro, _ = oracle.solve(C, f, g, **common)
-    st, res, X, u, v = run_dense(C, f, g, prec, **common)
+    st, res, X, u, v = run_dense(C, f, g, prec, engine=engine, **common)
     assert res["returned_average"] == ro["returned_average"]
     lim = 1e-13 if prec == P.OT_PREC_FP64 else 1e-6
     assert np.abs(X - Xo).max() <= lim * np.abs(Xo).max()
@@ -130,14 +138,16 @@ def highs_opt(C, f, g):
     return r.fun
 
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("seed", range(4))
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
-def test_config1_solve_matches_oracle_and_exact_lp(seed, prec):
+def test_config1_solve_matches_oracle_and_exact_lp(seed, prec, engine):
     inst = gen.config_instance(1, seed)
     C = inst.dense_cost()
     _, _, _, ref, _ = oracle.solve(C, inst.f, inst.g, tol=1e-6)
     opt = highs_opt(C, inst.f, inst.g)
-    st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, time_limit_s=60.0))
+    st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, engine=engine,
+                                                   time_limit_s=60.0))
     torch.cuda.synchronize()
     assert st == P.OT_OK, P.ot_last_error()
     assert res["rel_kkt"] <= 1e-6
@@ -210,9 +220,10 @@ def test_config3_grid_4096_verified_and_bracketed():
 
 # ----------------------------------------------------------- cost sources
 
+@pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
 @pytest.mark.parametrize("which", ["grid", "points_sq", "points_eu"])
-def test_stored_and_regenerated_costs_give_identical_plans(prec, which):
+def test_stored_and_regenerated_costs_give_identical_plans(prec, which, engine):
     if which == "grid":
         inst = gen.grid_pair(5, 12, tol=1e-6)
     elif which == "points_sq":
@@ -221,7 +232,7 @@ def test_stored_and_regenerated_costs_give_identical_plans(prec, which):
         inst = gen.gmm_euclid(5, 120, 70, tol=1e-6)
     outs = []
     for store in (0, 1):
-        st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec,
+        st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, engine=engine,
                                                        time_limit_s=60.0), store=store)
         assert st == P.OT_OK, P.ot_last_error()
         outs.append((res, out["X"].cpu().numpy()))
@@ -320,6 +331,51 @@ def test_unbalanced_or_negative_marginals_are_invalid():
 
 
 # ----------------------------------------------------------- determinism, batch, plumbing
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_resident_and_grid_engines_agree(prec):
+    """The two execution paths run the same method with different summation orders: both
+    meet the tolerance (confirmed by the oracle's KKT) and their objectives agree to the
+    accuracy the tolerance fixes; each path is deterministic."""
+    for inst in (gen.points_sqeuclid(31, 120, 200, tol=1e-6), gen.grid_pair(32, 11, tol=1e-6),
+                 gen.gmm_euclid(33, 250, 90, tol=1e-6)):
+        C = inst.dense_cost()
+        objs = []
+        for engine in ENGINES:
+            prm = P.params(tol=1e-6, precision=prec, engine=engine, time_limit_s=60.0)
+            st, res, out = P.solve_instance(inst, prm)
+            assert st == P.OT_OK, P.ot_last_error()
+            k = oracle.kkt(C, inst.f, inst.g, out["X"].double().cpu().numpy(),
+                           out["u"].cpu().numpy(), out["v"].cpu().numpy())
+            assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+            st2, res2, out2 = P.solve_instance(inst, prm)
+            assert res2["iterations"] == res["iterations"]
+            assert np.array_equal(out2["X"].cpu().numpy(), out["X"].cpu().numpy())
+            objs.append(res["objective"])
+        assert rel(objs[0], objs[1]) <= 5e-6
+
+
+def test_resident_instances_beside_grid_instances_in_one_batch():
+    """A batch whose instances straddle the resident threshold: the resident ones run on
+    their own stream beside the graph of the others, and every result equals its solo
+    solve."""
+    insts = [gen.points_sqeuclid(60 + i, m, n, tol=1e-5)
+             for i, (m, n) in enumerate([(64, 64), (300, 300), (180, 360), (700, 650), (20, 3000)])]
+    prm = P.params(tol=1e-5, precision=P.OT_PREC_FP32, time_limit_s=60.0)
+    probs, outs = [], []
+    for inst in insts:
+        pr, out = P.problem_from_instance(inst, tol=inst.tol)
+        probs.append(pr)
+        outs.append(out)
+    st, results = P.ot_solve_batch(probs, prm)
+    torch.cuda.synchronize()
+    assert st == P.OT_OK, P.ot_last_error()
+    for inst, out, rb in zip(insts, outs, results):
+        s1, r1, o1 = P.solve_instance(inst, prm, tol=inst.tol)
+        assert s1 == P.OT_OK
+        assert rb.iterations == r1["iterations"]
+        assert np.array_equal(out["X"].cpu().numpy(), o1["X"].cpu().numpy())
+
 
 def test_repeated_solves_are_bit_identical():
     inst = gen.grid_pair(8, 40)
