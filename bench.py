@@ -258,16 +258,17 @@ def batch_leg(P, count=256, seq_every=4):
     }
 
 
-def serving_leg(P, count=200, load=0.7, sat_count=24, budget_s=60.0, iter_cap=200000):
+def serving_leg(P, count=48, load=0.7, iter_cap=200000):
     """Continuous-batching server on a Poisson stream of mixed requests (points and images,
-    m, n log-uniform in [64, 16384], tol 1e-4 or 1e-6).  The saturated rate is measured by
-    submitting the first sat_count requests at once; the stream is then replayed at `load`
-    times that rate (capped to about budget_s of arrivals)."""
+    m, n log-uniform in [64, 16384], tol 1e-4 or 1e-6), first `count` requests of the
+    stream.  The saturated rate of this set is measured by submitting all of it at once;
+    the same requests are then replayed with the stream's arrival pattern at `load` times
+    that rate."""
     import torch
     from workloads import generators as gen
     FP32 = P.OT_PREC_FP32
     stream = gen.serving_stream(count=count)
-    prm = P.params(tol=1e-4, precision=FP32, time_limit_s=120.0, max_iters=iter_cap)
+    prm = P.params(tol=1e-4, precision=FP32, time_limit_s=300.0, max_iters=iter_cap)
     budget = 64 << 30
 
     def run(reqs):
@@ -283,38 +284,43 @@ def serving_leg(P, count=200, load=0.7, sat_count=24, budget_s=60.0, iter_cap=20
                 st, tk = srv.submit(pr)
                 if st != P.OT_OK:
                     raise RuntimeError(f"submit failed: {P.STATUS_NAMES.get(st)} {P.ot_last_error()}")
-            if srv.drain(600.0) != P.OT_OK:
+            if srv.drain(900.0) != P.OT_OK:
                 raise RuntimeError("server did not drain")
             for d in srv.poll(4096):
                 outs[d["ticket"]] = d
             return list(outs.values()), srv.stats()
 
-    sat = [(inst, 0.0) for _, inst in stream[:sat_count]]
-    done, _ = run(sat)
-    span = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
-    sat_rate = len(done) / span
+    done, _ = run([(inst, 0.0) for _, inst in stream])
+    span_sat = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
+    sat_rate = len(done) / span_sat
     rate = load * sat_rate
     base = 10.0                         # rate the stream's arrival times were drawn at
-    use = [(inst, t * base / rate) for t, inst in stream if t * base / rate <= budget_s]
-    log(f"serving: saturated {sat_rate:.2f} solves/s on the first {sat_count}; replaying "
-        f"{len(use)} requests at {rate:.2f}/s")
-    done, stats = run(use)
+    log(f"serving: {len(done)} requests submitted at once finish in {span_sat:.2f} s "
+        f"({sat_rate:.3f} solves/s); replaying them at {rate:.3f}/s")
+    done, stats = run([(inst, t * base / rate) for t, inst in stream])
     lat = [d["t_done"] - d["t_submit"] for d in done]
     wait = [d["t_admit"] - d["t_submit"] for d in done]
     span = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
     capped = sum(1 for d in done if d["status"] == P.OT_NOT_CONVERGED)
     bad = sum(1 for d in done if d["status"] not in (P.OT_OK, P.OT_NOT_CONVERGED))
+    sizes = [inst.m * inst.n for _, inst in stream]
+    small = sorted(sizes)[len(sizes) // 2]
+    order = sorted(done, key=lambda d: d["ticket"])   # tickets follow submission order
+    lat_small = [d["t_done"] - d["t_submit"] for d, sz in zip(order, sizes) if sz <= small]
+    lat_large = [d["t_done"] - d["t_submit"] for d, sz in zip(order, sizes) if sz > small]
     log(f"serving: {len(done)} done in {span:.2f} s, latency p50 {percentile(lat, 50):.3f} s "
         f"p99 {percentile(lat, 99):.3f} s; max running {stats['max_running']}")
     return {
-        "workload": f"Poisson stream (master seed 500), first {len(use)} of {count} requests: 90% "
-                    "point clouds in [0,1]^2 with squared-Euclidean cost, 10% blob images with "
-                    "side log-uniform in [8,128]; m,n log-uniform in [64,16384]; tol 1e-4 or "
-                    f"1e-6; FP32 plan; iteration cap {iter_cap}",
+        "workload": f"Poisson stream (master seed 500), first {count} requests: 90% point clouds "
+                    "in [0,1]^2 with squared-Euclidean cost, 10% blob images with side "
+                    "log-uniform in [8,128]; m,n log-uniform in [64,16384]; tol 1e-4 or 1e-6; "
+                    f"FP32 plan; iteration cap {iter_cap}",
         "requests": len(done), "rate_per_s": round(rate, 3),
         "saturated_solves_per_s": round(sat_rate, 3), "load": load,
         "latency_p50_s": round(percentile(lat, 50), 4),
         "latency_p99_s": round(percentile(lat, 99), 4),
+        "latency_p50_smaller_half_s": round(percentile(lat_small, 50), 4),
+        "latency_p50_larger_half_s": round(percentile(lat_large, 50), 4),
         "queue_wait_p50_s": round(percentile(wait, 50), 4),
         "queue_wait_p99_s": round(percentile(wait, 99), 4),
         "solves_per_s": round(len(done) / span, 3),
@@ -333,10 +339,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200,
-                    help="length of the request stream (the full stream is 2000)")
-    ap.add_argument("--serve-budget-s", type=float, default=60.0,
-                    help="replay at most this many seconds of arrivals")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests taken from the stream (the full stream is 2000)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the workload of the counter runs (see profiles/)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_LOG"))
@@ -427,8 +431,7 @@ def main():
             log(f"form {name}: {dtf:.3f} s, {rf['iterations']} iterations")
 
     batch = None if args.no_batch else batch_leg(P)
-    serving = None if args.no_serving else serving_leg(P, count=args.serve_requests,
-                                                       budget_s=args.serve_budget_s)
+    serving = None if args.no_serving else serving_leg(P, count=args.serve_requests)
     cpu = None if args.no_cpu else cpu_baseline(inst)
 
     line = {

@@ -74,8 +74,21 @@ ot_status fail(ot_status st, const std::string &msg)
 constexpr size_t kAlign = 256;
 constexpr int kMaxGrid = 4096;
 constexpr int kMaxGroups = 24;   // precisions x columns-per-lane x cost sources
-// device counts: tiles per grid variant, combine entries, instances per resident variant
-constexpr int kNumCounts = 2 * kMaxGroups + 1;
+// Instances that run on the whole GPU are split by size into lanes; each lane has its own
+// graph and stream, so small instances keep their short slots while large ones run.
+constexpr int kLanes = 3;
+constexpr int64_t kLaneMax[kLanes - 1] = {(int64_t)1 << 18, (int64_t)1 << 24};   // plan entries
+// device counts: per lane the tiles of each variant and the combine entries, then the
+// instances of each resident variant
+constexpr int kLaneCounts = kMaxGroups + 1;
+constexpr int kNumCounts = kLanes * kLaneCounts + kMaxGroups;
+
+int lane_of(int64_t elems)
+{
+    int l = 0;
+    while (l < kLanes - 1 && elems > kLaneMax[l]) ++l;
+    return l;
+}
 
 enum { ST_RUNNING = -1 };
 
@@ -94,6 +107,7 @@ struct Layout {
     int cost = C_STORED, dim = 0, side = 0;
     bool stored = true;
     bool resident = false;    // one work-group runs the whole instance
+    int lane = 0;             // size lane (instances on the whole GPU)
     size_t es = 4;
     size_t off_X[4] = {0, 0, 0, 0}, off_C = 0, off_xs = 0, off_ys = 0, off_f = 0, off_g = 0;
     size_t off_rowv = 0, off_colv = 0, off_rowpart = 0, off_colpart = 0;
@@ -179,6 +193,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     if (L.rows < 16 || L.rows % 16) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 16");
     // a resident instance is one row block: its work-group streams every row of a band
     if (L.resident) L.rows = (int)L.m_alloc;
+    L.lane = lane_of(elems);
     L.nrb = (int)((pb.m + L.rows - 1) / L.rows);
     const int64_t nt = (int64_t)L.ncb * L.nrb;
     if (nt > (1 << 30)) return fail(OT_ERR_INVALID, "too many tiles");
@@ -417,8 +432,11 @@ public:
             return fail(OT_ERR_OOM, "arena too small for the engine tables");
         HIP_TRY(hipHostMalloc((void **)&h_ctl_, sizeof(Ctl) * (size_t)max_slots, hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void **)&h_counts_, sizeof(int32_t) * kNumCounts, hipHostMallocDefault));
-        // resident instances run on a second stream, beside the graph of the others
+        // resident instances run on a stream of their own, and so does every lane but the
+        // first (which uses the caller's stream), beside each other
         HIP_TRY(hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking));
+        lanes_[0].s = s_;
+        for (int l = 1; l < kLanes; ++l) HIP_TRY(hipStreamCreateWithFlags(&lanes_[l].s, hipStreamNonBlocking));
         for (int i = 0; i < max_slots; ++i) free_slots_.push_back(max_slots - 1 - i);
         for (auto &e : ev_) HIP_TRY(hipEventCreate(&e));
         return OT_OK;
@@ -445,20 +463,21 @@ public:
         return OT_OK;
     }
 
-    // Launch one block: `slots` iteration slots of the instances that run on the whole
-    // GPU (one graph launch) and, beside them on a second stream, up to `budget` slots of
-    // every resident instance (one launch per resident variant); then refresh the host
-    // mirror of the control blocks of the running instances.
-    ot_status run_block(int slots)
+    // Launch one block of about target_ms: for every lane a graph launch of its slots
+    // (slots_hint > 0 fixes the slot count, else each lane picks its own), and up to
+    // `budget` slots of every resident instance, all on their own streams beside each
+    // other; then refresh the host mirror of the control blocks of the running instances.
+    ot_status run_block(int slots_hint, double target_ms = 2.0)
     {
-        OT_TRY(sync_tables(slots));
-        const int budget = resident_budget(2.0);
+        OT_TRY(sync_tables(slots_hint, target_ms));
+        const int budget = resident_budget(target_ms);
         if (prm_.profile) {
-            // one variant at a time, every launch timed by events it stamps itself
+            // one launch at a time, every launch timed by events it stamps itself
             for (size_t gi = 0; gi < rgroups_.size(); ++gi) {
                 const RGroup &g = rgroups_[gi];
                 HIP_TRY(launch_resident(g.fp32, g.vec, g.cost, d_insts(), d_rlist() + g.first,
-                                        d_counts() + kMaxGroups + 1 + gi, g.cap, budget, s_, ev_[0], ev_[1]));
+                                        d_counts() + kLanes * kLaneCounts + gi, g.cap, budget, s_, ev_[0],
+                                        ev_[1]));
                 HIP_TRY(hipEventSynchronize(ev_[1]));
                 float t = 0.f;
                 HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
@@ -466,41 +485,46 @@ public:
                     if (r->L.resident && r->L.fp32 == g.fp32 && r->L.vec == g.vec && r->L.cost == g.cost)
                         r->pass_ms += t;
             }
-            for (int k = 0; k < slots && have_grid_; ++k) {
-                float a = 0.f, b = 0.f;
-                for (size_t gi = 0; gi < groups_.size(); ++gi) {
-                    const Group &g = groups_[gi];
-                    HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), d_tiles() + g.first,
-                                        d_counts() + gi, g.grid, s_, ev_[0], ev_[1]));
-                    HIP_TRY(hipEventSynchronize(ev_[1]));
-                    float t = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
-                    a += t;
-                }
-                HIP_TRY(launch_combine(d_insts(), d_combs(), d_counts() + kMaxGroups, comb_grid_, s_,
-                                       ev_[0], ev_[1]));
-                HIP_TRY(hipEventSynchronize(ev_[1]));
-                HIP_TRY(hipEventElapsedTime(&b, ev_[0], ev_[1]));
-                for (Req *r : active_)
-                    if (!r->L.resident && h_ctl_[r->slot].mode != M_IDLE) {
-                        r->pass_ms += a;
-                        r->comb_ms += b;
+            for (int l = 0; l < kLanes; ++l) {
+                Lane &ln = lanes_[l];
+                for (int k = 0; k < ln.slots && ln.active; ++k) {
+                    float a = 0.f, b = 0.f;
+                    for (size_t gi = 0; gi < ln.groups.size(); ++gi) {
+                        const Group &g = ln.groups[gi];
+                        HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln) + g.first,
+                                            d_counts() + l * kLaneCounts + gi, g.grid, s_, ev_[0], ev_[1]));
+                        HIP_TRY(hipEventSynchronize(ev_[1]));
+                        float t = 0.f;
+                        HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
+                        a += t;
                     }
-                for (Req *r : active_)
-                    HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
-                HIP_TRY(hipStreamSynchronize(s_));
+                    HIP_TRY(launch_combine(d_insts(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups,
+                                           ln.comb_grid, s_, ev_[0], ev_[1]));
+                    HIP_TRY(hipEventSynchronize(ev_[1]));
+                    HIP_TRY(hipEventElapsedTime(&b, ev_[0], ev_[1]));
+                    for (Req *r : active_)
+                        if (!r->L.resident && r->L.lane == l && h_ctl_[r->slot].mode != M_IDLE) {
+                            r->pass_ms += a;
+                            r->comb_ms += b;
+                        }
+                    for (Req *r : active_)
+                        HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+                    HIP_TRY(hipStreamSynchronize(s_));
+                }
             }
         } else {
             for (size_t gi = 0; gi < rgroups_.size(); ++gi) {
                 const RGroup &g = rgroups_[gi];
                 HIP_TRY(launch_resident(g.fp32, g.vec, g.cost, d_insts(), d_rlist() + g.first,
-                                        d_counts() + kMaxGroups + 1 + gi, g.cap, budget, s2_));
+                                        d_counts() + kLanes * kLaneCounts + gi, g.cap, budget, s2_));
             }
-            if (have_grid_) HIP_TRY(hipGraphLaunch(exec_, s_));
+            for (int l = 0; l < kLanes; ++l)
+                if (lanes_[l].active) HIP_TRY(hipGraphLaunch(lanes_[l].exec, lanes_[l].s));
             HIP_TRY(hipStreamSynchronize(s2_));
+            for (int l = 1; l < kLanes; ++l) HIP_TRY(hipStreamSynchronize(lanes_[l].s));
         }
         for (Req *r : active_) {
-            r->slots_run += r->L.resident ? budget : slots;
+            r->slots_run += r->L.resident ? budget : lanes_[r->L.lane].slots;
             HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
         }
         HIP_TRY(hipStreamSynchronize(s_));
@@ -576,14 +600,15 @@ public:
     size_t arena_total() const { return arena_.total(); }
     int64_t launches() const { return launches_; }
 
-    // Slots per graph launch for the running set: about target_ms of streaming at
-    // roughly 5 TB/s, between 4 and 512 slots.
-    int auto_slots(double target_ms) const
+    // Slots per graph launch for the running instances of a lane: about target_ms of
+    // streaming at roughly 5 TB/s plus about 15 us of latency per slot, between 4 and 512.
+    int auto_slots(int lane, double target_ms) const
     {
         double bytes = 0.0;
         for (const Req *r : active_)
-            if (!r->L.resident) bytes += (double)r->L.m * (double)r->L.ld * (double)r->L.es * 5.0;
-        const double t_slot = bytes / 5e12 + 8e-6;
+            if (!r->L.resident && r->L.lane == lane)
+                bytes += (double)r->L.m * (double)r->L.ld * (double)r->L.es * 5.0;
+        const double t_slot = bytes / 5e12 + 15e-6;
         int s = (int)(target_ms * 1e-3 / t_slot);
         return std::max(4, std::min(512, s));
     }
@@ -606,10 +631,18 @@ public:
     {
         if (s2_) (void)hipStreamSynchronize(s2_);
         if (s_) (void)hipStreamSynchronize(s_);
-        if (exec_) (void)hipGraphExecDestroy(exec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
-        exec_ = nullptr;
-        graph_ = nullptr;
+        for (int l = 0; l < kLanes; ++l) {
+            Lane &ln = lanes_[l];
+            if (l > 0 && ln.s) {
+                (void)hipStreamSynchronize(ln.s);
+                (void)hipStreamDestroy(ln.s);
+            }
+            ln.s = nullptr;
+            if (ln.exec) (void)hipGraphExecDestroy(ln.exec);
+            if (ln.graph) (void)hipGraphDestroy(ln.graph);
+            ln.exec = nullptr;
+            ln.graph = nullptr;
+        }
         for (auto &e : ev_) {
             if (e) (void)hipEventDestroy(e);
             e = nullptr;
@@ -638,11 +671,24 @@ private:
         int fp32, vec, cost;
         int first, cap;   // region of the resident list; cap is also the launch grid
     };
+    // A size lane: its tile and combine tables, and the graph of its slots.
+    struct Lane {
+        std::vector<Group> groups;
+        size_t off_tiles = 0, off_combs = 0;
+        int64_t tile_cap = 0, comb_cap = 0;
+        int comb_grid = 1;
+        hipStream_t s = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        int slots = 0;          // slots per launch (of the captured graph)
+        int captured = 0;       // slots in the captured graph
+        bool active = false;    // has running instances
+    };
 
     Inst *d_insts() const { return (Inst *)(base_ + off_insts_); }
     int32_t *d_counts() const { return (int32_t *)(base_ + off_counts_); }
-    Tile *d_tiles() const { return (Tile *)(base_ + off_tiles_); }
-    CombEntry *d_combs() const { return (CombEntry *)(base_ + off_combs_); }
+    Tile *tiles(const Lane &ln) const { return (Tile *)(base_ + ln.off_tiles); }
+    CombEntry *combs(const Lane &ln) const { return (CombEntry *)(base_ + ln.off_combs); }
     int32_t *d_rlist() const { return (int32_t *)(base_ + off_rlist_); }
 
     ot_status copy_outputs(Req &r, const Ctl &c)
@@ -758,24 +804,35 @@ private:
         return OT_OK;
     }
 
-    // Rebuild the tile and combine tables of the running set; capture the graph again when
-    // the variant layout changed or the tables had to grow.
-    ot_status sync_tables(int slots)
+    // Rebuild the tile, combine and resident tables of the running set; in each lane,
+    // capture the graph again when its variant layout changed, a table had to grow or its
+    // slot count changed.  A lane keeps its slot count unless the work asks for more than
+    // twice or less than half of it (every new count needs a new capture).
+    ot_status sync_tables(int slots_hint, double target_ms)
     {
-        if (!dirty_ && (exec_ || prm_.profile || !have_grid_) && slots == graph_slots_) return OT_OK;
+        int want[kLanes];
+        bool change = dirty_;
+        for (int l = 0; l < kLanes; ++l) {
+            Lane &ln = lanes_[l];
+            int w = slots_hint > 0 ? slots_hint : auto_slots(l, target_ms);
+            if (slots_hint <= 0 && ln.slots > 0 && w <= 2 * ln.slots && 2 * w >= ln.slots) w = ln.slots;
+            want[l] = w;
+            change |= w != ln.slots;
+        }
+        if (!change) return OT_OK;
         struct Key {
             int fp32, vec, cost;
         };
-        std::vector<Key> keys, rkeys;
         auto key_of = [](std::vector<Key> &ks, const Layout &l) {
             for (size_t k = 0; k < ks.size(); ++k)
                 if (ks[k].fp32 == l.fp32 && ks[k].vec == l.vec && ks[k].cost == l.cost) return k;
             ks.push_back({l.fp32, l.vec, l.cost});
             return ks.size() - 1;
         };
-        std::vector<std::vector<Tile>> per;
+        std::vector<Key> keys[kLanes], rkeys;
+        std::vector<std::vector<Tile>> per[kLanes];
+        std::vector<CombEntry> cmb[kLanes];
         std::vector<std::vector<int32_t>> rper;
-        std::vector<CombEntry> combs;
         for (Req *r : active_) {
             const Layout &l = r->L;
             if (l.resident) {
@@ -784,17 +841,18 @@ private:
                 rper[gi].push_back(r->slot);
                 continue;
             }
-            const size_t gi = key_of(keys, l);
-            if (per.size() < keys.size()) per.resize(keys.size());
+            const int ln = l.lane;
+            const size_t gi = key_of(keys[ln], l);
+            if (per[ln].size() < keys[ln].size()) per[ln].resize(keys[ln].size());
             for (int rb = 0; rb < l.nrb; ++rb)
-                for (int cb = 0; cb < l.ncb; ++cb) per[gi].push_back(Tile{r->slot, rb, cb, rb * l.ncb + cb});
+                for (int cb = 0; cb < l.ncb; ++cb) per[ln][gi].push_back(Tile{r->slot, rb, cb, rb * l.ncb + cb});
             int local = 0;
-            for (int64_t i = 0; i < l.m; i += kCombEntries) combs.push_back(CombEntry{r->slot, 0, (int)i, local++});
-            for (int64_t j = 0; j < l.n; j += kCombEntries) combs.push_back(CombEntry{r->slot, 1, (int)j, local++});
+            for (int64_t i = 0; i < l.m; i += kCombEntries) cmb[ln].push_back(CombEntry{r->slot, 0, (int)i, local++});
+            for (int64_t j = 0; j < l.n; j += kCombEntries) cmb[ln].push_back(CombEntry{r->slot, 1, (int)j, local++});
         }
-        if ((int)keys.size() > kMaxGroups || (int)rkeys.size() > kMaxGroups)
-            return fail(OT_ERR_INVALID, "too many kernel variants in one run");
-        have_grid_ = !keys.empty();
+        if ((int)rkeys.size() > kMaxGroups) return fail(OT_ERR_INVALID, "too many kernel variants in one run");
+        for (int l = 0; l < kLanes; ++l)
+            if ((int)keys[l].size() > kMaxGroups) return fail(OT_ERR_INVALID, "too many kernel variants in one run");
 
         // resident lists: one region per variant (launched directly, no graph)
         {
@@ -819,93 +877,106 @@ private:
             }
         }
 
-        // grid tables: keep the current layout when every variant still fits its region
-        bool relayout = have_grid_ && ((!exec_ && !prm_.profile) || slots != graph_slots_ ||
-                                       (int64_t)combs.size() > comb_cap_);
-        std::vector<int> map(keys.size(), -1);
-        for (size_t k = 0; k < keys.size(); ++k) {
-            for (size_t g = 0; g < groups_.size(); ++g)
-                if (groups_[g].fp32 == keys[k].fp32 && groups_[g].vec == keys[k].vec &&
-                    groups_[g].cost == keys[k].cost && (int64_t)per[k].size() <= groups_[g].cap)
-                    map[k] = (int)g;
-            if (map[k] < 0) relayout = true;
-        }
-        if (relayout) {
-            std::vector<Group> ng;
-            int64_t total = 0;
-            for (size_t k = 0; k < keys.size(); ++k) {
-                // room to spare so that instances joining later rarely force a new capture
-                const int cap = (int)std::max<int64_t>(256, (int64_t)per[k].size() * 3 / 2 + 64);
-                ng.push_back(Group{keys[k].fp32, keys[k].vec, keys[k].cost, (int)total, cap,
-                                   std::min(cap, kMaxGrid)});
-                map[k] = (int)k;
-                total += cap;
-            }
-            const int64_t ccap = std::max<int64_t>(256, (int64_t)combs.size() * 3 / 2 + 64);
-            if (total > tile_cap_) {
-                if (tile_cap_) arena_.release(off_tiles_, sizeof(Tile) * (size_t)tile_cap_);
-                tile_cap_ = 0;
-                if (!arena_.alloc(sizeof(Tile) * (size_t)total, &off_tiles_))
-                    return fail(OT_ERR_OOM, "arena too small for the tile table");
-                tile_cap_ = total;
-            }
-            if (ccap > comb_cap_) {
-                if (comb_cap_) arena_.release(off_combs_, sizeof(CombEntry) * (size_t)comb_cap_);
-                comb_cap_ = 0;
-                if (!arena_.alloc(sizeof(CombEntry) * (size_t)ccap, &off_combs_))
-                    return fail(OT_ERR_OOM, "arena too small for the combine table");
-                comb_cap_ = ccap;
-            }
-            groups_ = ng;
-            comb_grid_ = (int)std::min<int64_t>(comb_cap_, kMaxGrid);
-        }
         for (int g = 0; g < kNumCounts; ++g) h_counts_[g] = 0;
-        for (size_t k = 0; k < keys.size(); ++k) {
-            const Group &g = groups_[map[k]];
-            if (!per[k].empty())
-                HIP_TRY(hipMemcpyAsync(d_tiles() + g.first, per[k].data(), sizeof(Tile) * per[k].size(),
+        bool recapture[kLanes];
+        for (int l = 0; l < kLanes; ++l) {
+            Lane &ln = lanes_[l];
+            recapture[l] = false;
+            ln.active = !keys[l].empty();
+            ln.slots = want[l];
+            if (!ln.active) continue;
+            // keep the current layout when every variant still fits its region
+            bool relayout = (!ln.exec && !prm_.profile) || ln.slots != ln.captured ||
+                            (int64_t)cmb[l].size() > ln.comb_cap;
+            std::vector<int> map(keys[l].size(), -1);
+            for (size_t k = 0; k < keys[l].size(); ++k) {
+                for (size_t g = 0; g < ln.groups.size(); ++g)
+                    if (ln.groups[g].fp32 == keys[l][k].fp32 && ln.groups[g].vec == keys[l][k].vec &&
+                        ln.groups[g].cost == keys[l][k].cost && (int64_t)per[l][k].size() <= ln.groups[g].cap)
+                        map[k] = (int)g;
+                if (map[k] < 0) relayout = true;
+            }
+            if (relayout) {
+                std::vector<Group> ng;
+                int64_t total = 0;
+                for (size_t k = 0; k < keys[l].size(); ++k) {
+                    // room to spare so that instances joining later rarely force a new capture
+                    const int cap = (int)std::max<int64_t>(256, (int64_t)per[l][k].size() * 3 / 2 + 64);
+                    ng.push_back(Group{keys[l][k].fp32, keys[l][k].vec, keys[l][k].cost, (int)total, cap,
+                                       std::min(cap, kMaxGrid)});
+                    map[k] = (int)k;
+                    total += cap;
+                }
+                const int64_t ccap = std::max<int64_t>(256, (int64_t)cmb[l].size() * 3 / 2 + 64);
+                if (total > ln.tile_cap) {
+                    if (ln.tile_cap) arena_.release(ln.off_tiles, sizeof(Tile) * (size_t)ln.tile_cap);
+                    ln.tile_cap = 0;
+                    if (!arena_.alloc(sizeof(Tile) * (size_t)total, &ln.off_tiles))
+                        return fail(OT_ERR_OOM, "arena too small for the tile table");
+                    ln.tile_cap = total;
+                }
+                if (ccap > ln.comb_cap) {
+                    if (ln.comb_cap) arena_.release(ln.off_combs, sizeof(CombEntry) * (size_t)ln.comb_cap);
+                    ln.comb_cap = 0;
+                    if (!arena_.alloc(sizeof(CombEntry) * (size_t)ccap, &ln.off_combs))
+                        return fail(OT_ERR_OOM, "arena too small for the combine table");
+                    ln.comb_cap = ccap;
+                }
+                ln.groups = ng;
+                ln.comb_grid = (int)std::min<int64_t>(ln.comb_cap, kMaxGrid);
+                recapture[l] = !prm_.profile;
+            }
+            for (size_t k = 0; k < keys[l].size(); ++k) {
+                const Group &g = ln.groups[map[k]];
+                if (!per[l][k].empty())
+                    HIP_TRY(hipMemcpyAsync(tiles(ln) + g.first, per[l][k].data(), sizeof(Tile) * per[l][k].size(),
+                                           hipMemcpyHostToDevice, s_));
+                h_counts_[l * kLaneCounts + map[k]] = (int32_t)per[l][k].size();
+            }
+            if (!cmb[l].empty())
+                HIP_TRY(hipMemcpyAsync(combs(ln), cmb[l].data(), sizeof(CombEntry) * cmb[l].size(),
                                        hipMemcpyHostToDevice, s_));
-            h_counts_[map[k]] = (int32_t)per[k].size();
+            h_counts_[l * kLaneCounts + kMaxGroups] = (int32_t)cmb[l].size();
         }
-        if (!combs.empty())
-            HIP_TRY(hipMemcpyAsync(d_combs(), combs.data(), sizeof(CombEntry) * combs.size(),
-                                   hipMemcpyHostToDevice, s_));
-        h_counts_[kMaxGroups] = (int32_t)combs.size();
-        for (size_t k = 0; k < rkeys.size(); ++k) h_counts_[kMaxGroups + 1 + k] = (int32_t)rper[k].size();
+        for (size_t k = 0; k < rkeys.size(); ++k) h_counts_[kLanes * kLaneCounts + k] = (int32_t)rper[k].size();
         HIP_TRY(hipMemcpyAsync(d_counts(), h_counts_, sizeof(int32_t) * kNumCounts, hipMemcpyHostToDevice, s_));
         HIP_TRY(hipStreamSynchronize(s_));   // the host tables above are temporaries
         dirty_ = false;
-        if (relayout && !prm_.profile) OT_TRY(capture(slots));
-        graph_slots_ = slots;
+        for (int l = 0; l < kLanes; ++l)
+            if (recapture[l]) OT_TRY(capture(l));
         return OT_OK;
     }
 
-    ot_status capture(int slots)
+    ot_status capture(int l)
     {
-        if (exec_) (void)hipGraphExecDestroy(exec_);
-        if (graph_) (void)hipGraphDestroy(graph_);
-        exec_ = nullptr;
-        graph_ = nullptr;
+        Lane &ln = lanes_[l];
+        if (ln.exec) (void)hipGraphExecDestroy(ln.exec);
+        if (ln.graph) (void)hipGraphDestroy(ln.graph);
+        ln.exec = nullptr;
+        ln.graph = nullptr;
+        ln.captured = 0;
         // relaxed: other threads (callers submitting to a server) may use the runtime while
         // this thread captures
-        HIP_TRY(hipStreamBeginCapture(s_, hipStreamCaptureModeRelaxed));
+        HIP_TRY(hipStreamBeginCapture(ln.s, hipStreamCaptureModeRelaxed));
         hipError_t e = hipSuccess;
-        for (int sl = 0; sl < slots && e == hipSuccess; ++sl) {
-            for (size_t gi = 0; gi < groups_.size() && e == hipSuccess; ++gi) {
-                const Group &g = groups_[gi];
-                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), d_tiles() + g.first, d_counts() + gi,
-                                g.grid, s_);
+        for (int sl = 0; sl < ln.slots && e == hipSuccess; ++sl) {
+            for (size_t gi = 0; gi < ln.groups.size() && e == hipSuccess; ++gi) {
+                const Group &g = ln.groups[gi];
+                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln) + g.first,
+                                d_counts() + l * kLaneCounts + gi, g.grid, ln.s);
             }
-            if (e == hipSuccess) e = launch_combine(d_insts(), d_combs(), d_counts() + kMaxGroups, comb_grid_, s_);
+            if (e == hipSuccess)
+                e = launch_combine(d_insts(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups, ln.comb_grid, ln.s);
         }
         hipGraph_t g = nullptr;
-        const hipError_t e2 = hipStreamEndCapture(s_, &g);
+        const hipError_t e2 = hipStreamEndCapture(ln.s, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return fail(OT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
         }
-        graph_ = g;
-        HIP_TRY(hipGraphInstantiate(&exec_, graph_, nullptr, nullptr, 0));
+        ln.graph = g;
+        HIP_TRY(hipGraphInstantiate(&ln.exec, ln.graph, nullptr, nullptr, 0));
+        ln.captured = ln.slots;
         return OT_OK;
     }
 
@@ -917,20 +988,15 @@ private:
     int max_slots_ = 0;
     std::vector<int> free_slots_;
     std::vector<Req *> active_;
-    size_t off_insts_ = 0, off_counts_ = 0, off_tiles_ = 0, off_combs_ = 0, off_rlist_ = 0;
-    int64_t tile_cap_ = 0, comb_cap_ = 0, rlist_cap_ = 0;
-    std::vector<Group> groups_;
+    size_t off_insts_ = 0, off_counts_ = 0, off_rlist_ = 0;
+    int64_t rlist_cap_ = 0;
+    Lane lanes_[kLanes];
     std::vector<RGroup> rgroups_;
-    bool have_grid_ = false;
     hipStream_t s2_ = nullptr;
-    int comb_grid_ = 1;
     bool dirty_ = true;
-    int graph_slots_ = 0;
     Ctl *h_ctl_ = nullptr;
     int32_t *h_counts_ = nullptr;
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t exec_ = nullptr;
-    hipEvent_t ev_[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_[2] = {nullptr, nullptr};
     int64_t launches_ = 0;
 };
 
@@ -947,14 +1013,17 @@ struct Planned {
 ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, Planned &P)
 {
     P.L.resize(count);
-    int64_t combs = 0;
-    std::vector<std::pair<std::tuple<int, int, int>, int64_t>> per;
+    int64_t combs[kLanes] = {};
+    bool used[kLanes] = {};
+    std::vector<std::pair<std::tuple<int, int, int, int>, int64_t>> per;
     for (int i = 0; i < count; ++i) {
         ot_status st = plan_instance(probs[i], prm, P.L[i]);
         if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
         const Layout &l = P.L[i];
-        combs += l.ncomb;
-        auto key = std::make_tuple(l.fp32, l.vec, l.cost);
+        if (l.resident) continue;
+        combs[l.lane] += l.ncomb;
+        used[l.lane] = true;
+        auto key = std::make_tuple(l.lane, l.fp32, l.vec, l.cost);
         bool seen = false;
         for (auto &kv : per)
             if (kv.first == key) {
@@ -965,10 +1034,14 @@ ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, P
     }
     size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(int32_t) * kNumCounts);
     for (auto &l : P.L) total += align_up(l.bytes);
-    int64_t tcap = 0;
-    for (auto &kv : per) tcap += std::max<int64_t>(256, kv.second * 3 / 2 + 64);
-    const int64_t ccap = std::max<int64_t>(256, combs * 3 / 2 + 64);
-    total += align_up(sizeof(Tile) * (size_t)tcap) + align_up(sizeof(CombEntry) * (size_t)ccap);
+    // each lane's tile and combine tables, sized as sync_tables sizes them
+    int64_t tcap[kLanes] = {};
+    for (auto &kv : per) tcap[std::get<0>(kv.first)] += std::max<int64_t>(256, kv.second * 3 / 2 + 64);
+    for (int l = 0; l < kLanes; ++l) {
+        if (!used[l]) continue;
+        const int64_t ccap = std::max<int64_t>(256, combs[l] * 3 / 2 + 64);
+        total += align_up(sizeof(Tile) * (size_t)tcap[l]) + align_up(sizeof(CombEntry) * (size_t)ccap);
+    }
     // resident lists, sized as sync_tables sizes them at most
     total += align_up(sizeof(int32_t) * (size_t)(((int64_t)count + 64 * kMaxGroups) * 3 / 2 + 64));
     P.total = total;
@@ -1001,11 +1074,10 @@ ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot
         if (st != OT_OK)
             return fail(st == OT_ERR_BUSY ? OT_ERR_OOM : st, "instance " + std::to_string(i) + ": " + g_err);
     }
-    const int slots = prm.graph_slots > 0 ? prm.graph_slots : E.auto_slots(2.0);
     bool stop_sent = false;
     ot_status hard = OT_OK;
     while (!E.active().empty()) {
-        ot_status st = E.run_block(prm.profile ? 1 : slots);
+        ot_status st = E.run_block(prm.profile ? 1 : prm.graph_slots);
         if (st != OT_OK) return st;
         std::vector<Req *> fin, stuck;
         for (Req *r : E.active()) {
@@ -1086,7 +1158,6 @@ struct ot_server {
     void loop()
     {
         (void)hipSetDevice(device);
-        int slots = 0;
         while (true) {
             {
                 std::unique_lock<std::mutex> lk(mu);
@@ -1124,12 +1195,7 @@ struct ot_server {
                 arena_peak = (int64_t)E.arena_peak();
             }
             if (running.empty()) continue;
-            int want = cfg.params.graph_slots > 0 ? cfg.params.graph_slots
-                                                  : E.auto_slots(cfg.block_ms > 0 ? cfg.block_ms : 2.0);
-            // change the slot count only when the work changed a lot (a new slot count
-            // needs a new graph capture)
-            if (slots == 0 || want > 2 * slots || 2 * want < slots) slots = want;
-            const ot_status st = E.run_block(slots);
+            const ot_status st = E.run_block(cfg.params.graph_slots, cfg.block_ms > 0 ? cfg.block_ms : 2.0);
             if (st != OT_OK) {
                 std::lock_guard<std::mutex> lk(mu);
                 thread_error = g_err;
