@@ -195,6 +195,33 @@ ot_status ot_solve(const ot_problem *prob, const ot_params *prm, ot_result *res,
 ot_status ot_solve_batch(const ot_problem *probs, int32_t count, const ot_params *prm,
                          ot_result *res, void *stream);
 
+/* ---- rounding to a feasible plan and the certified bracket ---------------------------
+ *
+ * Algorithm 3 (Section 3.2; Altschuler et al.'s rounding) maps an approximately feasible
+ * plan X to an exactly feasible X_feas: rows scaled by min(f_i/(X1)_i, 1), then columns by
+ * min(g_j/(X^T 1)_j, 1), then the rank-one correction err_r err_c^T / ||err_r||_1; Lemma
+ * lem:round bounds ||X_feas - X||_1 by 2 (||f - X1||_1 + ||g - X^T 1||_1).  The paper
+ * reports every result on the rounded plan (Section 5.1).  With any duals u, the
+ * c-transform v_j = min_i (C_ij - u_i) makes (u, v) dual feasible, so
+ *     lower = f^T u + g^T v  <=  OPT  <=  upper = <C, X_feas>   (weak duality).
+ * Everything is computed in FP64 with the FP64 cost (stored or regenerated). */
+typedef struct {
+    double upper;            /* <C, X_feas>, the cost of a feasible plan (>= OPT)        */
+    double lower;            /* f^T u + g^T v with v the c-transform of u (<= OPT)       */
+    double l1_change;        /* ||X_feas - X||_1                                         */
+    double marginal_l1;      /* ||f - X1||_1 + ||g - X^T 1||_1 of the input plan          */
+    double feas_violation;   /* max_i |(X_feas 1)_i - f_i|, max_j |(X_feas^T 1)_j - g_j|  */
+} ot_bracket;
+
+/* Round the plan X of `prob` (m x n, row stride n, FP32 when precision is OT_PREC_FP32,
+ * else FP64; host or device) and bound the optimal value with the duals u (length m, FP64,
+ * host or device).  X_feas: nullable m x n FP64 output (host or device).  Uses its own
+ * device workspace (about five FP64 m x n buffers), released before returning;
+ * synchronous on `stream` (nullable).  OT_ERR_INVALID for a null argument, an unknown
+ * precision or an invalid problem. */
+ot_status ot_round(const ot_problem *prob, int32_t precision, const void *X, const double *u,
+                   double *X_feas, ot_bracket *out, void *stream);
+
 /* ---- serving: continuous batching of arriving solves --------------------------------
  *
  * A server owns one device arena of hbm_budget_bytes and a scheduler thread.  Submitted

@@ -18,10 +18,10 @@ from ._abi import (  # noqa: F401
     OT_OK, OT_ERR_INVALID, OT_ERR_OOM, OT_ERR_DEVICE, OT_NOT_CONVERGED, OT_ERR_NUMERIC,
     OT_ERR_BUSY, OT_PREC_FP64, OT_PREC_FP32, OT_COST_DENSE, OT_COST_POINTS_SQEUCLID,
     OT_COST_POINTS_EUCLID, OT_COST_GRID_SQEUCLID, OtCost, OtParams, OtProblem, OtResult,
-    OtServerCfg, OtCompletion, OtServerStats, STATUS_NAMES,
+    OtServerCfg, OtCompletion, OtServerStats, OtBracket, STATUS_NAMES,
 )
 
-__all__ = ["ot_params_default", "ot_workspace_size", "ot_solve", "ot_solve_batch",
+__all__ = ["ot_params_default", "ot_workspace_size", "ot_solve", "ot_solve_batch", "ot_round",
            "ot_last_error", "ot_version", "ot_server_create", "ot_server_submit",
            "ot_server_poll", "ot_server_drain", "ot_server_get_stats", "ot_server_destroy",
            "params", "problem", "solve_instance", "problem_from_instance", "Server"]
@@ -131,6 +131,17 @@ def ot_solve_batch(probs, prm: OtParams, stream=None):
     res = (OtResult * len(probs))()
     st = _abi.load().ot_solve_batch(arr, len(probs), ct.byref(prm), res, stream)
     return int(st), list(res)
+
+
+def ot_round(prob: Problem, precision, X, u, X_feas=None, stream=None):
+    """Algorithm 3 on the plan X and the certified bracket from the duals u.
+    Returns (status, dict with upper, lower, l1_change, marginal_l1, feas_violation)."""
+    out = OtBracket()
+    _check_f64(u, "u")
+    _check_f64(X_feas, "X_feas")
+    st = _abi.load().ot_round(ct.byref(prob.raw), precision, _ptr(X), _ptr(u), _ptr(X_feas),
+                              ct.byref(out), stream)
+    return int(st), out.as_dict()
 
 
 def ot_server_create(hbm_budget_bytes, max_active=64, max_queue=0, block_ms=0.0, prm=None):

@@ -124,6 +124,19 @@ class OtResult(ct.Structure):
         return d
 
 
+class OtBracket(ct.Structure):
+    _fields_ = [
+        ("upper", ct.c_double),
+        ("lower", ct.c_double),
+        ("l1_change", ct.c_double),
+        ("marginal_l1", ct.c_double),
+        ("feas_violation", ct.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class OtServerCfg(ct.Structure):
     _fields_ = [
         ("hbm_budget_bytes", ct.c_size_t),
@@ -166,6 +179,8 @@ SIGNATURES = {
                             ct.c_void_p, ct.c_size_t, ct.c_void_p]),
     "ot_solve_batch": (ct.c_int, [ct.POINTER(OtProblem), ct.c_int32, ct.POINTER(OtParams),
                                   ct.POINTER(OtResult), ct.c_void_p]),
+    "ot_round": (ct.c_int, [ct.POINTER(OtProblem), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                            ct.POINTER(OtBracket), ct.c_void_p]),
     "ot_server_create": (ct.c_int, [ct.POINTER(OtServerCfg), ct.POINTER(ct.c_void_p)]),
     "ot_server_submit": (ct.c_int, [ct.c_void_p, ct.POINTER(OtProblem), ct.POINTER(ct.c_uint64)]),
     "ot_server_poll": (ct.c_int, [ct.c_void_p, ct.POINTER(OtCompletion), ct.c_int32,

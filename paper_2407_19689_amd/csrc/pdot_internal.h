@@ -35,6 +35,9 @@ constexpr int kNS = 6;            // per-tile scalars
 constexpr int kNC = 8;            // per-combine-entry scalars
 constexpr int kNB = kNC + kNS;    // combine record: entry scalars, then its share of tile scalars
 
+// scalars of the rounding passes (in combscal of the rounding instance)
+enum { RD_MARG = 0, RD_L1 = 1, RD_UPPER = 2, RD_CHANGE = 3, RD_LOWER = 4, RD_VIOL = 5 };
+
 // tile scalar slots
 enum { TS_DX2 = 0, TS_DRES = 1, TS_DRESB = 2, TS_POBJ = 3, TS_POBJB = 4, TS_AUX = 5 };
 // combine scalar slots

@@ -1108,6 +1108,242 @@ void k_resident(const Inst *__restrict__ insts, const int32_t *__restrict__ list
     }
 }
 
+// ------------------------------------------------------------------ rounding and bracket
+
+// Rounding of an approximately feasible plan to an exactly feasible one (Algorithm 3,
+// Section 3.2) and the certified bracket of the optimal value, on an FP64 copy of the plan
+// in an instance workspace (plan in X[0], duals u in p[0], the FP64 cost stored or
+// regenerated).  Four tiled passes, each followed by a one-work-group vector step:
+//   1. X 1 and X^T 1                    -> x_i = min(f_i / (X 1)_i, 1)
+//   2. column sums of D_x X             -> y_j = min(g_j / (D_x X)^T 1)_j, 1)
+//   3. row and column sums of D_x X D_y -> err_r = f - ..., err_c = g - ..., ||err_r||_1
+//   4. X_feas = D_x X D_y + err_r err_c^T / ||err_r||_1 (written when asked), <C, X_feas>,
+//      ||X_feas - X||_1, the sums of X_feas, and min_i (C_ij - u_i) per column
+// Vectors: x in rs[0], y in cs[0], err_r in rs[1], err_c in cs[1], the c-transform in csb;
+// the column minima of pass 4 use the free plan buffer X[1]; scalars in combscal[0..15].
+// Every sum runs in a fixed order.
+template <int COST>
+__device__ __forceinline__ double cost64(const PDOT_CONST Inst &I, int64_t i, int64_t j)
+{
+    if constexpr (COST == C_STORED) {
+        return gp((const double *)I.C)[i * I.ld + j];
+    } else if constexpr (COST == C_GRID_SQ) {
+        const uint32_t s = (uint32_t)I.side;
+        return grid_cost<double>((float)(int)((uint32_t)i / s), (float)(int)((uint32_t)i % s),
+                                 (float)(int)((uint32_t)j / s), (float)(int)((uint32_t)j % s), I.scale,
+                                 (float)I.scale);
+    } else {
+        double xi[3] = {0.0, 0.0, 0.0}, yj[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k < I.dim) {
+                xi[k] = gp(I.xs)[i * I.dim + k];
+                yj[k] = gp(I.ys)[j * I.dim + k];
+            }
+        double d = sqdist(xi, yj, I.dim);
+        if constexpr (COST == C_PTS_EU) d = sqrt(d);
+        return d;
+    }
+}
+
+template <int COST, int PHASE>
+__global__ __launch_bounds__(kWG) void k_round_tiles(const Inst *__restrict__ inst, double *__restrict__ xfeas)
+{
+#pragma clang fp contract(off)
+    const PDOT_CONST Inst &I = *cp(inst);
+    __shared__ double cl[3][2][64];
+    __shared__ double sl[4][2];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t m = I.m, n = I.n, ld = I.ld;
+    const PDOT_GLOBAL double *X = gp((const double *)I.X[0]);
+    const PDOT_GLOBAL double *xr = gp((const double *)I.rs[0]);
+    const PDOT_GLOBAL double *yc = gp((const double *)I.cs[0]);
+    const PDOT_GLOBAL double *er = gp((const double *)I.rs[1]);
+    const PDOT_GLOBAL double *ec = gp((const double *)I.cs[1]);
+    const PDOT_GLOBAL double *u = gp((const double *)I.p[0]);
+    PDOT_GLOBAL double *rowpart = gp(I.rowpart);
+    PDOT_GLOBAL double *colpart = gp(I.colpart);
+    PDOT_GLOBAL double *colmin = gp((double *)I.X[1]);
+    const double l1 = PHASE == 4 ? gp((const double *)I.combscal)[RD_L1] : 0.0;
+    constexpr double kInf = __builtin_huge_val();
+    for (int t = blockIdx.x; t < I.ntiles; t += gridDim.x) {
+        const int rb = t / I.ncb, cb = t % I.ncb;
+        const int64_t i0 = (int64_t)rb * I.rows, ie = min(m, i0 + (int64_t)I.rows);
+        double csum[2] = {0.0, 0.0}, cmin[2] = {kInf, kInf};
+        double s_up = 0.0, s_ch = 0.0;
+        int64_t jj[2];
+        bool ok[2];
+        double ycol[2] = {1.0, 1.0}, ecol[2] = {0.0, 0.0};
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            jj[v] = (int64_t)cb * 128 + lane * 2 + v;
+            ok[v] = jj[v] < n;
+            if (ok[v] && PHASE >= 3) ycol[v] = yc[jj[v]];
+            if (ok[v] && PHASE == 4) ecol[v] = ec[jj[v]];
+        }
+        for (int64_t i = i0 + wave; i < ie; i += 4) {
+            const double xi = PHASE >= 2 ? xr[i] : 1.0;
+            const double eri = PHASE == 4 ? er[i] : 0.0;
+            const double ui = PHASE == 4 ? u[i] : 0.0;
+            double rsum = 0.0;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                if (!ok[v]) continue;
+                const int64_t j = jj[v];
+                const double x = X[i * ld + j];
+                double val = x;
+                if (PHASE >= 2) val = xi * x;
+                if (PHASE >= 3) val = val * ycol[v];
+                if (PHASE == 4) {
+                    if (l1 > 0.0) val = val + eri * ecol[v] / l1;
+                    const double c = cost64<COST>(I, i, j);
+                    s_up = fma(c, val, s_up);
+                    s_ch += fabs(val - x);
+                    const double d = c - ui;
+                    cmin[v] = d < cmin[v] ? d : cmin[v];
+                    if (xfeas) xfeas[i * n + j] = val;
+                }
+                rsum += val;
+                csum[v] += val;
+            }
+            if (PHASE != 2) {
+                const double r = wave_sum_to63(rsum);
+                if (lane == 63) rowpart[(int64_t)cb * m + i] = r;
+            }
+        }
+        // column partials (sums; minima in pass 4): the four waves in a fixed order
+        if (wave > 0) {
+            cl[wave - 1][0][lane] = csum[0];
+            cl[wave - 1][1][lane] = csum[1];
+        }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const double sv = ((csum[v] + cl[0][v][lane]) + cl[1][v][lane]) + cl[2][v][lane];
+                if (ok[v]) colpart[(int64_t)rb * n + jj[v]] = sv;
+            }
+        }
+        __syncthreads();
+        if (PHASE == 4) {
+            if (wave > 0) {
+                cl[wave - 1][0][lane] = cmin[0];
+                cl[wave - 1][1][lane] = cmin[1];
+            }
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    double mv = cmin[v];
+                    for (int w = 0; w < 3; ++w) mv = cl[w][v][lane] < mv ? cl[w][v][lane] : mv;
+                    if (ok[v]) colmin[(int64_t)rb * n + jj[v]] = mv;
+                }
+            }
+            const double a = wave_sum_to63(s_up), b = wave_sum_to63(s_ch);
+            if (lane == 63) {
+                sl[wave][0] = a;
+                sl[wave][1] = b;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                PDOT_GLOBAL double *ts = gp(I.tilescal) + (int64_t)t * kNS;
+                ts[0] = ((sl[0][0] + sl[1][0]) + sl[2][0]) + sl[3][0];
+                ts[1] = ((sl[0][1] + sl[1][1]) + sl[2][1]) + sl[3][1];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// The vector step after each pass (one work-group; thread t takes indices t, t+256, ...;
+// per-thread terms are combined by DPP and LDS in a fixed order).
+template <int PHASE>
+__global__ __launch_bounds__(kWG) void k_round_vec(const Inst *__restrict__ inst)
+{
+#pragma clang fp contract(off)
+    const PDOT_CONST Inst &I = *cp(inst);
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t m = I.m, n = I.n;
+    const PDOT_GLOBAL double *rowpart = gp((const double *)I.rowpart);
+    const PDOT_GLOBAL double *colpart = gp((const double *)I.colpart);
+    const PDOT_GLOBAL double *f = gp(I.f);
+    const PDOT_GLOBAL double *g = gp(I.g);
+    PDOT_GLOBAL double *sc = gp(I.combscal);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};   // sums, or a maximum in acc[3]
+    for (int64_t i = threadIdx.x; i < m && PHASE != 2; i += kWG) {
+        double r = 0.0;
+        for (int c = 0; c < I.ncb; ++c) r += rowpart[(int64_t)c * m + i];
+        const double fi = f[i];
+        if (PHASE == 1) {
+            gp((double *)I.rs[0])[i] = r > 0.0 ? fmin(fi / r, 1.0) : 1.0;
+            acc[0] += fabs(fi - r);
+        } else if (PHASE == 3) {
+            const double e = fi - r;
+            gp((double *)I.rs[1])[i] = e;
+            acc[1] += fabs(e);
+        } else {
+            acc[3] = fmax(acc[3], fabs(r - fi));
+            acc[2] = fma(fi, gp((const double *)I.p[0])[i], acc[2]);
+        }
+    }
+    for (int64_t j = threadIdx.x; j < n; j += kWG) {
+        double c = 0.0;
+        for (int r = 0; r < I.nrb; ++r) c += colpart[(int64_t)r * n + j];
+        const double gj = g[j];
+        if (PHASE == 1) {
+            acc[0] += fabs(gj - c);
+        } else if (PHASE == 2) {
+            gp((double *)I.cs[0])[j] = c > 0.0 ? fmin(gj / c, 1.0) : 1.0;
+        } else if (PHASE == 3) {
+            gp((double *)I.cs[1])[j] = gj - c;
+        } else {
+            acc[3] = fmax(acc[3], fabs(c - gj));
+            const PDOT_GLOBAL double *cm = gp((const double *)I.X[1]);
+            double v = cm[j];
+            for (int r = 1; r < I.nrb; ++r) v = cm[(int64_t)r * n + j] < v ? cm[(int64_t)r * n + j] : v;
+            gp((double *)I.csb)[j] = v;
+            acc[2] = fma(gj, v, acc[2]);
+        }
+    }
+    double r[4];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q] = wave_sum_to63(acc[q]);
+    // maximum over the wave: every lane's value, read by lane 63 through LDS
+    __shared__ double mx[kWG];
+    mx[threadIdx.x] = acc[3];
+    __syncthreads();
+    if (lane == 63) {
+        double v = 0.0;
+        for (int k = 0; k < 64; ++k) v = fmax(v, mx[wave * 64 + k]);
+        r[3] = v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wave][q] = r[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[4];
+        for (int q = 0; q < 3; ++q) t[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
+        t[3] = fmax(fmax(red[0][3], red[1][3]), fmax(red[2][3], red[3][3]));
+        if (PHASE == 1) sc[RD_MARG] = t[0];
+        if (PHASE == 3) sc[RD_L1] = t[1];
+        if (PHASE == 4) {
+            double up = 0.0, ch = 0.0;
+            const PDOT_GLOBAL double *ts = gp((const double *)I.tilescal);
+            for (int k = 0; k < I.ntiles; ++k) {
+                up += ts[(int64_t)k * kNS];
+                ch += ts[(int64_t)k * kNS + 1];
+            }
+            sc[RD_UPPER] = up;
+            sc[RD_CHANGE] = ch;
+            sc[RD_LOWER] = t[2];
+            sc[RD_VIOL] = t[3];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ setup kernels
 
 // Materialise the cost in the working precision with padding columns set to zero.
@@ -1247,6 +1483,53 @@ hipError_t launch_resident(int fp32, int vec, int cost, const Inst *insts, const
 {
     return fp32 ? launch_resident_t<float>(vec, cost, insts, list, count, grid, budget, s, ev0, ev1)
                 : launch_resident_t<double>(vec, cost, insts, list, count, grid, budget, s, ev0, ev1);
+}
+
+template <int COST>
+static hipError_t launch_round_cost(const Inst *inst, double *xfeas, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_round_tiles<COST, 1>), dim3(grid), dim3(kWG), 0, s, inst, (double *)nullptr);
+    hipLaunchKernelGGL(k_round_vec<1>, dim3(1), dim3(kWG), 0, s, inst);
+    hipLaunchKernelGGL((k_round_tiles<COST, 2>), dim3(grid), dim3(kWG), 0, s, inst, (double *)nullptr);
+    hipLaunchKernelGGL(k_round_vec<2>, dim3(1), dim3(kWG), 0, s, inst);
+    hipLaunchKernelGGL((k_round_tiles<COST, 3>), dim3(grid), dim3(kWG), 0, s, inst, (double *)nullptr);
+    hipLaunchKernelGGL(k_round_vec<3>, dim3(1), dim3(kWG), 0, s, inst);
+    hipLaunchKernelGGL((k_round_tiles<COST, 4>), dim3(grid), dim3(kWG), 0, s, inst, xfeas);
+    hipLaunchKernelGGL(k_round_vec<4>, dim3(1), dim3(kWG), 0, s, inst);
+    return hipGetLastError();
+}
+
+// FP32 plan (row stride n) widened into an FP64 buffer of row stride ld.
+__global__ __launch_bounds__(kWG) void k_widen(const float *__restrict__ src, int64_t m, int64_t n,
+                                               double *__restrict__ dst, int64_t ld)
+{
+    const int64_t total = m * n;
+    for (int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x; e < total; e += (int64_t)gridDim.x * kWG) {
+        const int64_t i = e / n, j = e % n;
+        dst[i * ld + j] = (double)src[e];
+    }
+}
+
+hipError_t launch_widen(const float *src, int64_t m, int64_t n, double *dst, int64_t ld, hipStream_t s)
+{
+    int64_t blocks = (m * n + kWG - 1) / kWG;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)blocks), dim3(kWG), 0, s, src, m, n, dst, ld);
+    return hipGetLastError();
+}
+
+// Rounding passes of one FP64 instance (inst: device pointer to its descriptor).
+hipError_t launch_round(int cost, const Inst *inst, int ntiles, double *xfeas, hipStream_t s)
+{
+    const int grid = ntiles < 65536 ? ntiles : 65536;
+    switch (cost) {
+    case C_STORED: return launch_round_cost<C_STORED>(inst, xfeas, grid, s);
+    case C_PTS_SQ: return launch_round_cost<C_PTS_SQ>(inst, xfeas, grid, s);
+    case C_PTS_EU: return launch_round_cost<C_PTS_EU>(inst, xfeas, grid, s);
+    case C_GRID_SQ: return launch_round_cost<C_GRID_SQ>(inst, xfeas, grid, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,

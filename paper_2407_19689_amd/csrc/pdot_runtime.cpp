@@ -44,6 +44,8 @@ hipError_t launch_resident(int fp32, int vec, int cost, const Inst *insts, const
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,
                               const double *src, int64_t ldc, const double *xs, const double *ys,
                               int dim, int side, double scale, hipStream_t s);
+hipError_t launch_round(int cost, const Inst *inst, int ntiles, double *xfeas, hipStream_t s);
+hipError_t launch_widen(const float *src, int64_t m, int64_t n, double *dst, int64_t ld, hipStream_t s);
 }  // namespace pdot
 
 using namespace pdot;
@@ -529,6 +531,35 @@ public:
         }
         HIP_TRY(hipStreamSynchronize(s_));
         ++launches_;
+        return OT_OK;
+    }
+
+    // Algorithm 3 and the certified bracket for an admitted FP64 instance: the plan X
+    // (row stride n, FP32 or FP64, host or device) goes to X[0], the duals u to p[0];
+    // X_feas (nullable, FP64, row stride n, host or device) receives the feasible plan;
+    // scal[6] receives the scalars (RD_* order).
+    ot_status round_instance(Req &r, const void *X, int x_fp32, const double *u, double *X_feas, double *scal)
+    {
+        const Layout &l = r.L;
+        Inst &I = r.I;
+        const size_t esx = x_fp32 ? 4 : 8;
+        if (x_fp32) {
+            // stage the FP32 plan in the (free) third plan buffer, then widen it
+            HIP_TRY(hipMemcpyAsync(I.X[2], X, esx * (size_t)(l.m * l.n), hipMemcpyDefault, s_));
+            HIP_TRY(launch_widen((const float *)I.X[2], l.m, l.n, (double *)I.X[0], l.ld, s_));
+        } else {
+            HIP_TRY(hipMemcpy2DAsync(I.X[0], sizeof(double) * l.ld, X, sizeof(double) * l.n,
+                                     sizeof(double) * l.n, l.m, hipMemcpyDefault, s_));
+        }
+        HIP_TRY(hipMemcpyAsync(I.p[0], u, sizeof(double) * l.m, hipMemcpyDefault, s_));
+        double *xf = nullptr;
+        const bool direct = X_feas && is_device_ptr(X_feas);
+        if (X_feas) xf = direct ? X_feas : (double *)I.X[2];   // X[2] holds m*n doubles
+        HIP_TRY(launch_round(l.cost, d_insts() + r.slot, l.ntiles, xf, s_));
+        HIP_TRY(hipMemcpyAsync(scal, I.combscal, sizeof(double) * 6, hipMemcpyDeviceToHost, s_));
+        if (X_feas && !direct)
+            HIP_TRY(hipMemcpyAsync(X_feas, xf, sizeof(double) * (size_t)(l.m * l.n), hipMemcpyDeviceToHost, s_));
+        HIP_TRY(hipStreamSynchronize(s_));
         return OT_OK;
     }
 
@@ -1295,6 +1326,47 @@ ot_status ot_solve_batch(const ot_problem *probs, int32_t count, const ot_params
 {
     if (!probs || !prm || count < 1) return fail(OT_ERR_INVALID, "null argument or empty batch");
     return run_fixed(probs, count, *prm, res, nullptr, 0, (hipStream_t)stream);
+}
+
+ot_status ot_round(const ot_problem *prob, int32_t precision, const void *X, const double *u,
+                   double *X_feas, ot_bracket *out, void *stream)
+{
+    if (!prob || !X || !u || !out) return fail(OT_ERR_INVALID, "null argument");
+    if (precision != OT_PREC_FP32 && precision != OT_PREC_FP64) return fail(OT_ERR_INVALID, "unknown precision");
+    // an FP64 instance (the paper's costs) on the whole-GPU layout, 128-column bands
+    ot_params prm;
+    ot_params_default(&prm);
+    prm.precision = OT_PREC_FP64;
+    prm.engine = 1;
+    ot_problem pb = *prob;
+    pb.tile_vec = 2;
+    pb.tile_rows = 0;
+    pb.X_out = nullptr;
+    pb.u_out = nullptr;
+    pb.v_out = nullptr;
+    Planned P;
+    OT_TRY(plan_fixed(&pb, 1, prm, P));
+    std::vector<double> fh, gh;
+    OT_TRY(fetch_host(pb.f, (size_t)pb.m, fh));
+    OT_TRY(fetch_host(pb.g, (size_t)pb.n, gh));
+    OT_TRY(validate_marginals(fh, gh));
+    Engine E;
+    OT_TRY(E.init(prm, (hipStream_t)stream, P.total, nullptr, 0, 1));
+    Req r;
+    r.L = P.L[0];
+    r.prob = pb;
+    r.tol = 1.0;
+    OT_TRY(E.admit(r));
+    double sc[6] = {0, 0, 0, 0, 0, 0};
+    OT_TRY(E.round_instance(r, X, precision == OT_PREC_FP32, u, X_feas, sc));
+    memset(out, 0, sizeof(*out));
+    out->marginal_l1 = sc[RD_MARG];
+    out->upper = sc[RD_UPPER];
+    out->l1_change = sc[RD_CHANGE];
+    out->lower = sc[RD_LOWER];
+    out->feas_violation = sc[RD_VIOL];
+    g_err.clear();
+    return OT_OK;
 }
 
 ot_status ot_server_create(const ot_server_cfg *cfg, ot_server **out)

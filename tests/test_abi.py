@@ -37,7 +37,8 @@ def test_ctypes_structs_match_c_layout(tmp_path):
     src = tmp_path / "layout.c"
     cls = {"ot_cost": P.OtCost, "ot_problem": P.OtProblem, "ot_params": P.OtParams,
            "ot_result": P.OtResult, "ot_server_cfg": P.OtServerCfg,
-           "ot_completion": P.OtCompletion, "ot_server_stats": P.OtServerStats}
+           "ot_completion": P.OtCompletion, "ot_server_stats": P.OtServerStats,
+           "ot_bracket": P.OtBracket}
     fields = {st: [f for f, _ in c._fields_] for st, c in cls.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){']
     for st, fl in fields.items():
@@ -127,4 +128,18 @@ def test_server_rejects_invalid_configuration_without_device_work():
     st, h = P.ot_server_create(1 << 30, max_active=0)
     assert st == P.OT_ERR_INVALID
     st, h = P.ot_server_create(1 << 30, max_active=4, prm=P.params(tol=-1.0))
+    assert st == P.OT_ERR_INVALID
+
+
+def test_round_rejects_invalid_arguments_without_device_work():
+    f, g, C = _dense(4, 5)
+    pr = P.problem(P.OT_COST_DENSE, 4, 5, f, g, C=C)
+    X = np.zeros((4, 5))
+    u = np.zeros(4)
+    st, _ = P.ot_round(pr, P.OT_PREC_FP64, None, u)
+    assert st == P.OT_ERR_INVALID
+    st, _ = P.ot_round(pr, 7, X, u)
+    assert st == P.OT_ERR_INVALID
+    bad = P.problem(P.OT_COST_DENSE, 4, 5, f * 2.0, g, C=C)
+    st, _ = P.ot_round(bad, P.OT_PREC_FP64, X, u)
     assert st == P.OT_ERR_INVALID

@@ -216,6 +216,12 @@ def test_config3_grid_4096_verified_and_bracketed():
     assert lb <= ub
     assert lb - 5e-6 * obj <= obj <= ub + 5e-6 * obj
     assert (ub - lb) / obj <= 1e-4
+    # the GPU's rounding and bracket of the same plan agree with the oracle's
+    pr, _ = P.problem_from_instance(inst, want_plan=False)
+    st, br = P.ot_round(pr, P.OT_PREC_FP32, out["X"], out["u"])
+    assert st == P.OT_OK, P.ot_last_error()
+    assert rel(br["lower"], lb) <= 1e-11 and rel(br["upper"], ub) <= 1e-11
+    assert br["feas_violation"] <= 1e-15
 
 
 # ----------------------------------------------------------- cost sources
@@ -375,6 +381,57 @@ def test_resident_instances_beside_grid_instances_in_one_batch():
         assert s1 == P.OT_OK
         assert rb.iterations == r1["iterations"]
         assert np.array_equal(out["X"].cpu().numpy(), o1["X"].cpu().numpy())
+
+
+# ----------------------------------------------------------- rounding and bracket
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+@pytest.mark.parametrize("which", ["dense", "grid", "points_eu"])
+def test_rounding_and_bracket_match_oracle(prec, which):
+    """Algorithm 3 on the GPU equals the oracle's rounding of the same plan (FP64, different
+    summation order), the bracket equals the oracle's weak-duality bound and the cost of the
+    rounded plan, the rounded plan is feasible to rounding error, and Lemma lem:round's
+    bound on the change holds."""
+    if which == "dense":
+        C, f, g = random_problem(21, 70, 130)
+        inst = None
+    elif which == "grid":
+        inst = gen.grid_pair(22, 12, tol=1e-4)
+    else:
+        inst = gen.gmm_euclid(23, 150, 90, tol=1e-4)
+    prm = P.params(tol=1e-4, precision=prec, time_limit_s=60.0)
+    if inst is None:
+        st, res, X, u, v = run_dense(C, f, g, prec, tol=1e-4)
+        pr = P.problem(P.OT_COST_DENSE, 70, 130, dev(f), dev(g), C=dev(C))
+        Xin = X.astype(np.float32) if prec == P.OT_PREC_FP32 else X
+    else:
+        C, f, g = inst.dense_cost(), inst.f, inst.g
+        st, res, out = P.solve_instance(inst, prm)
+        X = out["X"].double().cpu().numpy()
+        u = out["u"].cpu().numpy()
+        pr, _ = P.problem_from_instance(inst, want_plan=False)
+        Xin = out["X"].cpu().numpy()
+    assert st == P.OT_OK, P.ot_last_error()
+    Xf = np.empty_like(X)
+    st, br = P.ot_round(pr, prec, Xin, u, X_feas=Xf)
+    assert st == P.OT_OK, P.ot_last_error()
+    ref = oracle.round_plan(f, g, X)
+    assert np.abs(Xf - ref).max() <= 1e-13 * np.abs(ref).max()
+    # err_r, err_c >= 0 in exact arithmetic; in FP64 an err_c_j can be a few ulps below 0
+    # where the scaled plan is 0, so entries are nonnegative up to rounding (as the oracle's)
+    assert Xf.min() >= -1e-14 * Xf.max()
+    lb = oracle.dual_lower_bound(C, f, g, u)
+    assert rel(br["lower"], lb) <= 1e-12
+    assert rel(br["upper"], float((C * ref).sum())) <= 1e-12
+    assert br["lower"] <= br["upper"]
+    assert br["feas_violation"] <= 1e-15
+    assert abs(Xf.sum(axis=1) - f).max() <= 1e-15 and abs(Xf.sum(axis=0) - g).max() <= 1e-15
+    marg = np.abs(f - X.sum(axis=1)).sum() + np.abs(g - X.sum(axis=0)).sum()
+    assert rel(br["marginal_l1"], marg) <= 1e-9
+    assert br["l1_change"] <= 2.0 * br["marginal_l1"] * (1 + 1e-12)
+    # the bracket contains the exact optimum
+    opt = highs_opt(C, f, g)
+    assert br["lower"] <= opt * (1 + 1e-12) and opt <= br["upper"] * (1 + 1e-12)
 
 
 def test_repeated_solves_are_bit_identical():
