@@ -65,6 +65,9 @@ typedef enum { OT_PREC_FP64 = 0, OT_PREC_FP32 = 1 } ot_precision;
  *   OT_COST_POINTS_EUCLID    C_ij = sqrt(sum_k (x_ik - y_jk)^2).
  *   OT_COST_GRID_SQEUCLID    m = n = side^2 pixels of an side x side image, pixel
  *                            i = (i / side, i % side); C_ij = scale * squared pixel distance.
+ *   OT_COST_GRID_L1, OT_COST_GRID_L2, OT_COST_GRID_LINF
+ *                            the same pixels with the l1, l2 and l-infinity distances (the
+ *                            C^1, C^2, C^inf costs of Section 5.1) times scale.
  * For the coordinate kinds `store` = 0 regenerates C_ij inside the iteration kernel from
  * the coordinates (no cost bytes streamed); `store` = 1 materialises C once in device
  * memory.  Both produce bit-identical cost values in the working precision. */
@@ -72,7 +75,10 @@ typedef enum {
     OT_COST_DENSE = 0,
     OT_COST_POINTS_SQEUCLID = 1,
     OT_COST_POINTS_EUCLID = 2,
-    OT_COST_GRID_SQEUCLID = 3
+    OT_COST_GRID_SQEUCLID = 3,
+    OT_COST_GRID_L1 = 4,
+    OT_COST_GRID_L2 = 5,
+    OT_COST_GRID_LINF = 6
 } ot_cost_kind;
 
 typedef struct {

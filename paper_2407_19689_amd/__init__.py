@@ -17,7 +17,8 @@ from . import _abi
 from ._abi import (  # noqa: F401
     OT_OK, OT_ERR_INVALID, OT_ERR_OOM, OT_ERR_DEVICE, OT_NOT_CONVERGED, OT_ERR_NUMERIC,
     OT_ERR_BUSY, OT_PREC_FP64, OT_PREC_FP32, OT_COST_DENSE, OT_COST_POINTS_SQEUCLID,
-    OT_COST_POINTS_EUCLID, OT_COST_GRID_SQEUCLID, OtCost, OtParams, OtProblem, OtResult,
+    OT_COST_POINTS_EUCLID, OT_COST_GRID_SQEUCLID, OT_COST_GRID_L1, OT_COST_GRID_L2,
+    OT_COST_GRID_LINF, OtCost, OtParams, OtProblem, OtResult,
     OtServerCfg, OtCompletion, OtServerStats, OtBracket, STATUS_NAMES,
 )
 
@@ -246,6 +247,9 @@ _KINDS = {
     "points_sqeuclid": OT_COST_POINTS_SQEUCLID,
     "points_euclid": OT_COST_POINTS_EUCLID,
     "grid_sqeuclid": OT_COST_GRID_SQEUCLID,
+    "grid_l1": OT_COST_GRID_L1,
+    "grid_l2": OT_COST_GRID_L2,
+    "grid_linf": OT_COST_GRID_LINF,
 }
 
 
@@ -268,7 +272,7 @@ def problem_from_instance(inst, device="cuda", precision=OT_PREC_FP32, store=0, 
                      tile_vec=tile_vec, tile_rows=tile_rows)
         return pr, out
     kind = _KINDS[inst.kind]
-    if kind == OT_COST_GRID_SQEUCLID:
+    if kind in (OT_COST_GRID_SQEUCLID, OT_COST_GRID_L1, OT_COST_GRID_L2, OT_COST_GRID_LINF):
         pr = problem(kind, inst.m, inst.n, f, g, side=inst.side, scale=inst.scale, store=store,
                      tol=tol, X_out=X, u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows)
     else:

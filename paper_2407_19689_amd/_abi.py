@@ -30,6 +30,9 @@ OT_COST_DENSE = 0
 OT_COST_POINTS_SQEUCLID = 1
 OT_COST_POINTS_EUCLID = 2
 OT_COST_GRID_SQEUCLID = 3
+OT_COST_GRID_L1 = 4
+OT_COST_GRID_L2 = 5
+OT_COST_GRID_LINF = 6
 
 _D = ct.POINTER(ct.c_double)
 

@@ -23,7 +23,10 @@ enum Mode : int32_t {
     M_VERIFY = 5    // exact KKT and objective of the returned triple
 };
 
-enum CostKind : int32_t { C_STORED = 0, C_PTS_SQ = 1, C_PTS_EU = 2, C_GRID_SQ = 3 };
+enum CostKind : int32_t {
+    C_STORED = 0, C_PTS_SQ = 1, C_PTS_EU = 2, C_GRID_SQ = 3, C_GRID_L1 = 4, C_GRID_L2 = 5, C_GRID_LINF = 6
+};
+constexpr bool is_grid(int c) { return c >= C_GRID_SQ && c <= C_GRID_LINF; }
 
 // Roles of the four m x ld plan buffers.  The trial buffer is never the current, the
 // average or the restart anchor, so a role swap replaces every copy.

@@ -129,31 +129,31 @@ __device__ __forceinline__ double round_to(double v)
     return (double)(TX)v;
 }
 
-// Grid kind, C_ij = scale * ((a_i - a_j)^2 + (b_i - b_j)^2) for pixels (a, b).  The
-// coordinates are small integers held exactly in floats.  FP64: exact integer distance
-// times scale, one FP64 rounding (the oracle's value).  FP32: the exact integer distance
-// times scale rounded to FP32, one FP32 rounding.
-template <typename TX>
+// Grid kinds, C_ij = scale * d(pixel_i, pixel_j) for pixels (a, b), with d the squared
+// Euclidean, l1, l2 or l-infinity distance.  The coordinates are small integers held
+// exactly in floats.  FP64: the integer distance exact, then the square root (l2) and the
+// product by scale each rounded once, in numpy's order (the oracle's value).  FP32: the
+// same steps in FP32 with scale rounded to FP32.
+template <typename TX, int COST>
 __device__ __forceinline__ double grid_cost(float ia, float ib, float ja, float jb, double scale,
-                                            float scale32);
-
-template <>
-__device__ __forceinline__ double grid_cost<double>(float ia, float ib, float ja, float jb,
-                                                    double scale, float)
+                                            float scale32)
 {
 #pragma clang fp contract(off)
-    const double da = (double)ia - (double)ja, db = (double)ib - (double)jb;
-    return (da * da + db * db) * scale;
-}
-
-template <>
-__device__ __forceinline__ double grid_cost<float>(float ia, float ib, float ja, float jb, double,
-                                                   float scale32)
-{
-#pragma clang fp contract(off)
-    const float da = ia - ja, db = ib - jb;
-    const float d2 = da * da + db * db;   // exact: an integer below 2^24
-    return (double)(d2 * scale32);
+    if constexpr (sizeof(TX) == 8) {
+        const double da = (double)ia - (double)ja, db = (double)ib - (double)jb;
+        if constexpr (COST == C_GRID_SQ) return (da * da + db * db) * scale;
+        else if constexpr (COST == C_GRID_L1) return (fabs(da) + fabs(db)) * scale;
+        else if constexpr (COST == C_GRID_L2) return sqrt(da * da + db * db) * scale;
+        else return fmax(fabs(da), fabs(db)) * scale;
+    } else {
+        const float da = ia - ja, db = ib - jb;
+        float d;
+        if constexpr (COST == C_GRID_SQ) d = da * da + db * db;   // exact: an integer below 2^24
+        else if constexpr (COST == C_GRID_L1) d = fabsf(da) + fabsf(db);
+        else if constexpr (COST == C_GRID_L2) d = sqrtf(da * da + db * db);
+        else d = fmaxf(fabsf(da), fabsf(db));
+        return (double)(d * scale32);
+    }
 }
 
 // 32-bit integer mixer "lowbias32" (C. Wellons, hash-prospector): a bijection on 32-bit
@@ -273,7 +273,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
     constexpr bool kTrial = MODE == M_TRIAL || MODE == M_FULL;
     constexpr bool kFold = MODE == M_FULL;
     constexpr bool kRowCol = kTrial || MODE == M_VERIFY;
-    constexpr bool kGrid = COST == C_GRID_SQ;
+    constexpr bool kGrid = is_grid(COST);
     constexpr bool kPts = COST == C_PTS_SQ || COST == C_PTS_EU;
     constexpr double kNegInf = -__builtin_huge_val();
 
@@ -411,7 +411,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                     if constexpr (COST == C_STORED) {
                         cd = (double)R.c[u][v];
                     } else if constexpr (kGrid) {
-                        cd = grid_cost<TX>(R.gia[u], R.gib[u], gja[v], gjb[v], scale, scale32);
+                        cd = grid_cost<TX, COST>(R.gia[u], R.gib[u], gja[v], gjb[v], scale, scale32);
                     } else {
                         double s2 = sqdist(R.xi[u], yc[v], dim);
                         if constexpr (COST == C_PTS_EU) s2 = sqrt(s2);
@@ -1127,11 +1127,11 @@ __device__ __forceinline__ double cost64(const PDOT_CONST Inst &I, int64_t i, in
 {
     if constexpr (COST == C_STORED) {
         return gp((const double *)I.C)[i * I.ld + j];
-    } else if constexpr (COST == C_GRID_SQ) {
+    } else if constexpr (is_grid(COST)) {
         const uint32_t s = (uint32_t)I.side;
-        return grid_cost<double>((float)(int)((uint32_t)i / s), (float)(int)((uint32_t)i % s),
-                                 (float)(int)((uint32_t)j / s), (float)(int)((uint32_t)j % s), I.scale,
-                                 (float)I.scale);
+        return grid_cost<double, COST>((float)(int)((uint32_t)i / s), (float)(int)((uint32_t)i % s),
+                                       (float)(int)((uint32_t)j / s), (float)(int)((uint32_t)j % s),
+                                       I.scale, (float)I.scale);
     } else {
         double xi[3] = {0.0, 0.0, 0.0}, yj[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1363,9 +1363,14 @@ __global__ __launch_bounds__(kWG) void k_materialize(TX *__restrict__ dst, int64
         if (j < n) {
             if (kind == C_STORED) {
                 v = src[i * ldc + j];
-            } else if (kind == C_GRID_SQ) {
-                v = grid_cost<TX>((float)(int)(i / side), (float)(int)(i % side), (float)(int)(j / side),
-                                  (float)(int)(j % side), scale, (float)scale);
+            } else if (is_grid(kind)) {
+                const float ia = (float)(int)(i / side), ib = (float)(int)(i % side);
+                const float ja = (float)(int)(j / side), jb = (float)(int)(j % side);
+                const float s32 = (float)scale;
+                if (kind == C_GRID_SQ) v = grid_cost<TX, C_GRID_SQ>(ia, ib, ja, jb, scale, s32);
+                else if (kind == C_GRID_L1) v = grid_cost<TX, C_GRID_L1>(ia, ib, ja, jb, scale, s32);
+                else if (kind == C_GRID_L2) v = grid_cost<TX, C_GRID_L2>(ia, ib, ja, jb, scale, s32);
+                else v = grid_cost<TX, C_GRID_LINF>(ia, ib, ja, jb, scale, s32);
             } else {
                 v = sqdist(xs + i * dim, ys + j * dim, dim);
                 if (kind == C_PTS_EU) v = sqrt(v);
@@ -1404,6 +1409,9 @@ static hipError_t launch_pass_vec(int cost, const Inst *insts, const Tile *tiles
     case C_PTS_SQ: return launch_k(k_pass<TX, VEC, C_PTS_SQ>, grid, insts, tiles, ntiles, s, ev0, ev1);
     case C_PTS_EU: return launch_k(k_pass<TX, VEC, C_PTS_EU>, grid, insts, tiles, ntiles, s, ev0, ev1);
     case C_GRID_SQ: return launch_k(k_pass<TX, VEC, C_GRID_SQ>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_L1: return launch_k(k_pass<TX, VEC, C_GRID_L1>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_L2: return launch_k(k_pass<TX, VEC, C_GRID_L2>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_LINF: return launch_k(k_pass<TX, VEC, C_GRID_LINF>, grid, insts, tiles, ntiles, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1461,6 +1469,9 @@ static hipError_t launch_resident_vec(int cost, const Inst *insts, const int32_t
     case C_PTS_SQ: return launch_r(k_resident<TX, VEC, C_PTS_SQ>, grid, insts, list, count, budget, s, ev0, ev1);
     case C_PTS_EU: return launch_r(k_resident<TX, VEC, C_PTS_EU>, grid, insts, list, count, budget, s, ev0, ev1);
     case C_GRID_SQ: return launch_r(k_resident<TX, VEC, C_GRID_SQ>, grid, insts, list, count, budget, s, ev0, ev1);
+    case C_GRID_L1: return launch_r(k_resident<TX, VEC, C_GRID_L1>, grid, insts, list, count, budget, s, ev0, ev1);
+    case C_GRID_L2: return launch_r(k_resident<TX, VEC, C_GRID_L2>, grid, insts, list, count, budget, s, ev0, ev1);
+    case C_GRID_LINF: return launch_r(k_resident<TX, VEC, C_GRID_LINF>, grid, insts, list, count, budget, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1528,6 +1539,9 @@ hipError_t launch_round(int cost, const Inst *inst, int ntiles, double *xfeas, h
     case C_PTS_SQ: return launch_round_cost<C_PTS_SQ>(inst, xfeas, grid, s);
     case C_PTS_EU: return launch_round_cost<C_PTS_EU>(inst, xfeas, grid, s);
     case C_GRID_SQ: return launch_round_cost<C_GRID_SQ>(inst, xfeas, grid, s);
+    case C_GRID_L1: return launch_round_cost<C_GRID_L1>(inst, xfeas, grid, s);
+    case C_GRID_L2: return launch_round_cost<C_GRID_L2>(inst, xfeas, grid, s);
+    case C_GRID_LINF: return launch_round_cost<C_GRID_LINF>(inst, xfeas, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

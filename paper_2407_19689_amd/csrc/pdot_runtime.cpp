@@ -50,6 +50,10 @@ hipError_t launch_widen(const float *src, int64_t m, int64_t n, double *dst, int
 
 using namespace pdot;
 
+static_assert(OT_COST_GRID_SQEUCLID == C_GRID_SQ && OT_COST_GRID_L1 == C_GRID_L1 &&
+                  OT_COST_GRID_L2 == C_GRID_L2 && OT_COST_GRID_LINF == C_GRID_LINF,
+              "grid cost kinds share their numbering with the kernels");
+
 namespace {
 
 thread_local std::string g_err;
@@ -172,12 +176,16 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
         L.cost = L.stored ? C_STORED : (c.kind == OT_COST_POINTS_SQEUCLID ? C_PTS_SQ : C_PTS_EU);
         break;
     case OT_COST_GRID_SQEUCLID:
+    case OT_COST_GRID_L1:
+    case OT_COST_GRID_L2:
+    case OT_COST_GRID_LINF:
         if (c.side < 1 || (int64_t)c.side * c.side != pb.m || pb.m != pb.n)
             return fail(OT_ERR_INVALID, "grid cost needs m = n = side^2");
         if (!std::isfinite(c.scale)) return fail(OT_ERR_INVALID, "grid scale not finite");
         L.side = c.side;
         L.stored = c.store != 0;
-        L.cost = L.stored ? C_STORED : C_GRID_SQ;
+        // the ABI's grid kinds and the kernels' cost kinds share their numbering
+        L.cost = L.stored ? C_STORED : (int)c.kind;
         break;
     default:
         return fail(OT_ERR_INVALID, "unknown cost kind");
@@ -810,8 +818,8 @@ private:
                     HIP_TRY(hipMemcpyAsync(tmp, C, bytes, hipMemcpyHostToDevice, s_));
                     src = (const double *)tmp;
                 }
-            } else if (pb.cost.kind == OT_COST_GRID_SQEUCLID) {
-                kind = C_GRID_SQ;
+            } else if (is_grid(pb.cost.kind)) {
+                kind = (int)pb.cost.kind;
             } else {
                 kind = pb.cost.kind == OT_COST_POINTS_SQEUCLID ? C_PTS_SQ : C_PTS_EU;
             }

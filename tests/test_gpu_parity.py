@@ -228,10 +228,13 @@ def test_config3_grid_4096_verified_and_bracketed():
 
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
-@pytest.mark.parametrize("which", ["grid", "points_sq", "points_eu"])
+@pytest.mark.parametrize("which", ["grid", "points_sq", "points_eu", "grid_l1", "grid_l2",
+                                   "grid_linf"])
 def test_stored_and_regenerated_costs_give_identical_plans(prec, which, engine):
     if which == "grid":
         inst = gen.grid_pair(5, 12, tol=1e-6)
+    elif which.startswith("grid_"):
+        inst = gen.grid_pair(5, 11, kind=which, tol=1e-6)
     elif which == "points_sq":
         inst = gen.points_sqeuclid(5, 90, 300, tol=1e-6)
     else:
@@ -249,11 +252,32 @@ def test_stored_and_regenerated_costs_give_identical_plans(prec, which, engine):
 def test_fp64_regenerated_cost_equals_dense_oracle_cost():
     """The FP64 kernel's cost equals numpy's FP64 cost bit for bit (no contraction), so the
     dense and regenerated FP64 solves follow the same trajectory."""
-    for inst in (gen.points_sqeuclid(3, 50, 70), gen.grid_pair(3, 10), gen.gmm_euclid(3, 40, 33)):
+    for inst in (gen.points_sqeuclid(3, 50, 70), gen.grid_pair(3, 10), gen.gmm_euclid(3, 40, 33),
+                 gen.grid_pair(3, 9, kind="grid_l1"), gen.grid_pair(3, 9, kind="grid_l2"),
+                 gen.grid_pair(3, 9, kind="grid_linf")):
         a = P.solve_instance(inst, P.params(tol=1e-6, precision=P.OT_PREC_FP64), dense=True)
         b = P.solve_instance(inst, P.params(tol=1e-6, precision=P.OT_PREC_FP64), dense=False)
         assert a[1]["iterations"] == b[1]["iterations"]
         assert np.array_equal(a[2]["X"].cpu().numpy(), b[2]["X"].cpu().numpy())
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+@pytest.mark.parametrize("kind", ["grid_l1", "grid_l2", "grid_linf"])
+def test_grid_norm_costs_match_oracle(prec, kind):
+    """The l1, l2 and l-infinity pixel costs of Section 5.1, regenerated in the kernel:
+    the oracle (dense FP64 cost) confirms the KKT error of the returned triple, and the
+    objective agrees with the oracle's at the same tolerance and with the exact optimum."""
+    inst = gen.grid_pair(17, 12, kind=kind, tol=1e-6)
+    C = inst.dense_cost()
+    _, _, _, ref, _ = oracle.solve(C, inst.f, inst.g, tol=1e-6, max_iters=400000)
+    opt = highs_opt(C, inst.f, inst.g)
+    st, res, out = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, time_limit_s=60.0))
+    assert st == P.OT_OK, P.ot_last_error()
+    k = oracle.kkt(C, inst.f, inst.g, out["X"].double().cpu().numpy(), out["u"].cpu().numpy(),
+                   out["v"].cpu().numpy())
+    assert k["rel_kkt"] <= 1e-6 * (1 + 1e-6)
+    assert rel(res["objective"], ref["objective"]) <= 5e-6
+    assert rel(res["objective"], opt) <= 5e-6
 
 
 # ----------------------------------------------------------- degenerate cases
