@@ -329,6 +329,50 @@ def serving_leg(P, count=48, load=0.7, iter_cap=200000):
     }
 
 
+def suite_leg(P, sizes=(32, 64), pairs=2, tol=1e-4, time_limit=60.0):
+    """DOTmark-shaped synthetic suite with the paper's reporting (Section 5.1): for every
+    resolution and norm (raw pixel distances C^1, C^2, C^inf), `pairs` image pairs of each
+    synthetic image class are solved to relative KKT `tol` (FP32 form) and rounded
+    (Algorithm 3).  Reported per resolution and norm: SGM10 of the solve times (an unsolved
+    instance counts at the time limit), the geometric mean of the duality gap
+    |<C, X_feas> - f^T u - g^T v| of the rounded plan, and the largest certified relative
+    gap (upper - lower) / upper."""
+    import math
+    import torch
+    from workloads import generators as gen
+    FP32 = P.OT_PREC_FP32
+    out = {}
+    for side in sizes:
+        for norm in ("l1", "l2", "linf"):
+            times, gaps, cgaps, its, solved = [], [], [], [], 0
+            for ci, cls in enumerate(gen.IMAGE_CLASSES):
+                for k in range(pairs):
+                    inst = gen.suite_pair(1000 * side + 10 * ci + k, side, cls, norm, tol=tol)
+                    prm = P.params(tol=tol, precision=FP32, time_limit_s=time_limit)
+                    pr, o = P.problem_from_instance(inst, precision=FP32)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    st, r = P.ot_solve(pr, prm)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t
+                    solved += st == P.OT_OK
+                    times.append(dt if st == P.OT_OK else time_limit)
+                    its.append(r.iterations)
+                    st2, br = P.ot_round(pr, FP32, o["X"], o["u"])
+                    if st2 == P.OT_OK:
+                        gaps.append(max(abs(br["upper"] - r.dual_objective), 1e-300))
+                        cgaps.append((br["upper"] - br["lower"]) / abs(br["upper"]))
+            sgm10 = math.exp(sum(math.log(t + 10.0) for t in times) / len(times)) - 10.0
+            row = {"instances": len(times), "solved": solved, "sgm10_s": round(sgm10, 5),
+                   "gap_geomean": math.exp(sum(math.log(g) for g in gaps) / len(gaps)),
+                   "certified_rel_gap_max": max(cgaps), "iterations_mean": round(sum(its) / len(its), 1)}
+            out[f"{side}x{side}_{norm}"] = row
+            log(f"suite {side}x{side} {norm}: {row}")
+    return {"workload": f"synthetic DOTmark-shaped suite: {len(gen.IMAGE_CLASSES)} image classes "
+                        f"x {pairs} pairs per resolution and norm, raw pixel distances, FP32, "
+                        f"tol {tol:g}, time limit {time_limit:g} s", "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +383,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-suite", action="store_true")
+    ap.add_argument("--suite-sizes", default="32,64",
+                    help="image sides of the synthetic suite (the paper's are 32,64,128)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests taken from the stream (the full stream is 2000)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -437,6 +484,21 @@ def main():
 
     forms = {}
     if not args.no_forms:
+        # ablation: Algorithm 2 as printed (constant step 1/(2 sqrt(m+n)), uniform average,
+        # basic restart to the average, fixed primal weight), to 1e-4, capped at 20 s
+        lit = P.params(tol=1e-4, precision=FP32, step_rule=1, restart_rule=1, avg_weighting=1,
+                       primal_weight_update=0, eta0=0.5 / (2 * 4096) ** 0.5, time_limit_s=20.0)
+        pr_l, _ = P.problem_from_instance(inst, precision=FP32, want_plan=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st_l, r_l = P.ot_solve(pr_l, lit)
+        torch.cuda.synchronize()
+        dt_l = time.perf_counter() - t
+        forms["paper_literal_tol1e-4"] = {"status": P.STATUS_NAMES.get(st_l), "seconds": round(dt_l, 4),
+                                          "iterations": r_l.iterations, "restarts": r_l.restarts,
+                                          "rel_kkt": r_l.rel_kkt}
+        log(f"paper-literal mode to 1e-4: {dt_l:.3f} s, {r_l.iterations} iterations "
+            f"({P.STATUS_NAMES.get(st_l)}), against {r4['iterations']} with the Section 5 rules")
         for name, prec, store in (("fp32_stored_cost", FP32, 1), ("fp64_regenerated_cost", FP64, 0),
                                   ("fp64_stored_cost", FP64, 1)):
             dtf, rf = gpu_solve(P, inst, args.tol, prec, store)
@@ -445,6 +507,7 @@ def main():
                            "objective": rf["objective"], "rel_kkt": rf["rel_kkt"]}
             log(f"form {name}: {dtf:.3f} s, {rf['iterations']} iterations")
 
+    suite = None if args.no_suite else suite_leg(P, sizes=tuple(int(x) for x in args.suite_sizes.split(",")))
     batch = None if args.no_batch else batch_leg(P)
     serving = None if args.no_serving else serving_leg(P, count=args.serve_requests)
     cpu = None if args.no_cpu else cpu_baseline(inst)
@@ -478,6 +541,7 @@ def main():
         "certified_bracket": bracket,
         "roofline": roof,
         "forms": forms,
+        "suite": suite,
         "batch": batch,
         "serving": serving,
         "cpu_baseline": cpu,

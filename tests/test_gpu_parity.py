@@ -280,6 +280,31 @@ def test_grid_norm_costs_match_oracle(prec, kind):
     assert rel(res["objective"], opt) <= 5e-6
 
 
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_paper_literal_mode_matches_oracle(prec):
+    """Algorithm 2 as printed: constant step eta = 1/(2 ||A||_2) = 1/(2 sqrt(m+n)) (the
+    theory's step), uniform averaging, the basic restart condition KKT(average) <=
+    beta KKT(restart point) with a restart to the average, fixed primal weight.  The oracle
+    in the same mode: the GPU's returned triple passes the oracle's KKT check, its objective
+    agrees, and in FP64 the two take the same number of iterations up to a few percent
+    (decisions compare KKT values computed with different summation orders; the FP32 form
+    rounds the plan every step and follows its own path)."""
+    inst = gen.config_instance(1, 2)
+    C = inst.dense_cost()
+    mode = dict(tol=1e-5, step_rule=1, restart_rule=1, avg_weighting=1, primal_weight_update=0,
+                eta0=0.5 / np.sqrt(inst.m + inst.n), beta_basic=0.2, max_iters=400000)
+    _, _, _, ref, _ = oracle.solve(C, inst.f, inst.g, **mode)
+    st, res, out = P.solve_instance(inst, P.params(precision=prec, time_limit_s=120.0, **mode))
+    assert st == P.OT_OK, P.ot_last_error()
+    k = oracle.kkt(C, inst.f, inst.g, out["X"].double().cpu().numpy(), out["u"].cpu().numpy(),
+                   out["v"].cpu().numpy())
+    assert k["rel_kkt"] <= 1e-5 * (1 + 1e-6)
+    assert rel(res["objective"], ref["objective"]) <= 5e-5
+    assert res["restarts"] >= 1 and ref["restarts"] >= 1
+    if prec == P.OT_PREC_FP64:
+        assert abs(res["iterations"] - ref["iterations"]) <= 0.05 * ref["iterations"] + 2
+
+
 # ----------------------------------------------------------- degenerate cases
 
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])

@@ -37,3 +37,21 @@ def test_committed_cache_holds_valid_shapes():
 def test_bucket():
     assert autotune.bucket(32, 2048) == (5, 11)
     assert autotune.bucket(1, 1) == (0, 0)
+
+
+def test_synthetic_image_classes_are_distributions():
+    """The stand-in image classes give nonnegative images summing to 1; the suite's costs
+    are the raw pixel distances of Section 5.1."""
+    import numpy as np
+    from workloads import generators as gen
+    for cls in gen.IMAGE_CLASSES:
+        inst = gen.suite_pair(3, 8, cls, "l1")
+        assert inst.m == inst.n == 64
+        for w in (inst.f, inst.g):
+            assert np.all(w > 0) and abs(w.sum() - 1.0) <= 1e-12
+    a = gen.suite_pair(3, 4, "blobs", "l1").dense_cost()
+    b = gen.suite_pair(3, 4, "blobs", "l2").dense_cost()
+    c = gen.suite_pair(3, 4, "blobs", "linf").dense_cost()
+    # pixels 0 = (0, 0) and 5 = (1, 1): distances 2, sqrt(2), 1
+    assert a[0, 5] == 2.0 and b[0, 5] == np.sqrt(2.0) and c[0, 5] == 1.0
+    assert a.max() == 6.0 and c.max() == 3.0

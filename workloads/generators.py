@@ -117,6 +117,61 @@ def grid_pair(seed: int, side: int, kind: str = "grid_sqeuclid", tol: float = 1e
                     meta={"seed": seed})
 
 
+# ---- synthetic image classes standing in for the DOTmark classes (Section 5.1), which are
+# not available; each returns a nonnegative s x s image, normalised to sum 1 (row-major)
+
+IMAGE_CLASSES = ("blobs", "white_noise", "cauchy", "smooth_field", "shapes")
+
+
+def class_image(rng, s: int, cls: str, floor: float = 1e-3):
+    a = np.arange(s, dtype=np.float64)
+    A, B = np.meshgrid(a, a, indexing="ij")
+    if cls == "blobs":
+        return blob_histogram(rng, s, floor=floor)
+    if cls == "white_noise":
+        H = rng.uniform(0.0, 1.0, size=(s, s))
+    elif cls == "cauchy":
+        # sum of three Cauchy bumps (heavy tails), widths U(0.02s, 0.2s)
+        H = np.zeros((s, s))
+        for _ in range(3):
+            ca, cb = rng.uniform(0.0, s - 1.0, size=2)
+            w = rng.uniform(0.02 * s, 0.2 * s)
+            H += 1.0 / (1.0 + ((A - ca) ** 2 + (B - cb) ** 2) / (w * w))
+    elif cls == "smooth_field":
+        # Gaussian random field: white noise filtered by a Gaussian of width s/8 (periodic)
+        k = np.fft.fftfreq(s)
+        K2 = k[:, None] ** 2 + k[None, :] ** 2
+        spec = np.fft.fft2(rng.normal(size=(s, s))) * np.exp(-2.0 * (np.pi * s / 8.0) ** 2 * K2)
+        H = np.real(np.fft.ifft2(spec))
+        H = np.exp(2.0 * H / H.std())          # log-normal field, positive
+    elif cls == "shapes":
+        # up to four filled rectangles and discs
+        H = np.zeros((s, s))
+        for _ in range(int(rng.integers(2, 5))):
+            ca, cb = rng.uniform(0.0, s - 1.0, size=2)
+            r = rng.uniform(0.05 * s, 0.25 * s)
+            if rng.uniform() < 0.5:
+                H += ((A - ca) ** 2 + (B - cb) ** 2 <= r * r)
+            else:
+                H += (np.abs(A - ca) <= r) & (np.abs(B - cb) <= 0.6 * r)
+    else:
+        raise ValueError(cls)
+    H = H / H.max() + floor
+    return _normalise(H.reshape(-1))
+
+
+def suite_pair(seed: int, side: int, cls: str, norm: str, tol: float = 1e-4):
+    """Two images of one class and the raw pixel distance of the given norm (C^1, C^2 or
+    C^inf of Section 5.1, not rescaled)."""
+    rng = np.random.default_rng(seed)
+    f = class_image(rng, side, cls)
+    g = class_image(rng, side, cls)
+    kind = {"l1": "grid_l1", "l2": "grid_l2", "linf": "grid_linf"}[norm]
+    mm = side * side
+    return Instance(mm, mm, f, g, kind, side=side, scale=1.0, tol=tol,
+                    meta={"seed": seed, "class": cls, "norm": norm})
+
+
 def gmm_points(rng, count: int, dim: int = 3, comps: int = 3):
     means = rng.normal(0.0, 2.0, size=(comps, dim))
     stds = rng.uniform(0.3, 1.0, size=comps)
