@@ -177,6 +177,12 @@ typedef struct {
                                   and cost streams; partial sums excluded)            */
     double pass_ms;            /* profile mode: summed duration of the pass launches   */
     double combine_ms;         /* profile mode: summed duration of the combine launches*/
+    int64_t verify_retries;    /* final verifications that found the returned arrays above
+                                  tol (the threshold was tightened and iteration resumed)  */
+    double kkt_estimate;       /* running relative-KKT estimate of the returned candidate
+                                  when the solver stopped (the verified value is rel_kkt) */
+    double estimate_parts[3];  /* its rel_primal, rel_dual, rel_gap                        */
+    double estimate_objective; /* its <C, X> (before the plan's storage rounding)          */
 } ot_result;
 
 /* Fill *prm with the defaults described above (precision OT_PREC_FP32). */

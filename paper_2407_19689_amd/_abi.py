@@ -119,11 +119,16 @@ class OtResult(ct.Structure):
         ("pass_bytes", ct.c_double),
         ("pass_ms", ct.c_double),
         ("combine_ms", ct.c_double),
+        ("verify_retries", ct.c_int64),
+        ("kkt_estimate", ct.c_double),
+        ("estimate_parts", ct.c_double * 3),
+        ("estimate_objective", ct.c_double),
     ]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["mode_passes"] = list(self.mode_passes)
+        d["estimate_parts"] = list(self.estimate_parts)
         return d
 
 

@@ -73,6 +73,7 @@ struct Ctl {
     double K_start, K_prev, K_cand;
     double norm_b, norm_c;
     double r_obj, r_dobj, r_relP, r_relD, r_relG, r_kkt;
+    double e_rel[3], e_obj;  // running estimate of the candidate (rel_P, rel_D, rel_G, <C,X>)
 };
 
 struct Inst {

@@ -447,7 +447,8 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                         s_pobj = fma(cd, xd, s_pobj);
                         // fold the current iterate into the running average; the averaged
                         // objective uses the value before storage rounding, like the
-                        // averaged row and column sums
+                        // averaged row and column sums (the final verification measures the
+                        // stored arrays)
                         const double xbd = (double)R.b[u][v];
                         const double xbn = first_fold ? xd : fma(a, xd, (1.0 - a) * xbd);
                         xb_out[v] = store_avg<TX>(xbn, hrow ^ hcol[v]);
@@ -547,10 +548,14 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PDOT_PASS_W
 void k_pass(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
             const int32_t *__restrict__ count)
 {
-    const int ntiles = *cp(count);
     __shared__ double lds[3 * 2 * 4 * 64 + 4 * kNS];
+    // The launch grid never exceeds the tile table's capacity, so the first tile entry is
+    // read before the count (both loads in flight); it is used only if it is in the count.
+    Tile next = cp(tiles)[blockIdx.x];
+    const int ntiles = *cp(count);
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile tl = cp(tiles)[t];
+        const Tile tl = next;
+        if (t + (int)gridDim.x < ntiles) next = cp(tiles)[t + gridDim.x];
         const PDOT_CONST Inst &I = cp(insts)[tl.inst];
         const Ctl st = *cp((const Ctl *)I.ctl);
         switch (st.mode) {
@@ -689,12 +694,15 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
         return;
     }
     if (mode == M_FULL) {
+        double ec[3], ea[3];
         const double kc = rel_kkt(P, c.norm_b, c.norm_c, cs[CS_PRES], ts[TS_DRES], ts[TS_POBJ],
-                                  cs[CS_DOBJ], nullptr);
+                                  cs[CS_DOBJ], ec);
         const double ka = rel_kkt(P, c.norm_b, c.norm_c, cs[CS_PRESB], ts[TS_DRESB],
-                                  ts[TS_POBJB], cs[CS_DOBJB], nullptr);
+                                  ts[TS_POBJB], cs[CS_DOBJB], ea);
         // restart candidate (Section 5): the current iterate only if strictly better
         c.cand_avg = !(kc < ka);
+        for (int q = 0; q < 3; ++q) c.e_rel[q] = c.cand_avg ? ea[q] : ec[q];
+        c.e_obj = c.cand_avg ? ts[TS_POBJB] : ts[TS_POBJ];
         double K = c.cand_avg ? ka : kc;
         if (!(K == K)) {
             c.status = ST_NUMERIC;
@@ -871,16 +879,20 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                                                  const CombEntry *__restrict__ ents,
                                                  const int32_t *__restrict__ count)
 {
-    const int nents = *cp(count);
     __shared__ double part[4][64];
     __shared__ double tsum[kNS];
     __shared__ double fin[4][kNB];
     __shared__ int is_last;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // The launch grid never exceeds the entry table's capacity: the first entry is read
+    // before the count (both loads in flight) and used only if it is in the count.
+    CombEntry next = cp(ents)[blockIdx.x];
+    const int nents = *cp(count);
 
     for (int e = blockIdx.x; e < nents; e += gridDim.x) {
-        const CombEntry E = cp(ents)[e];
+        const CombEntry E = next;
+        if (e + (int)gridDim.x < nents) next = cp(ents)[e + gridDim.x];
         const PDOT_CONST Inst &I = cp(insts)[E.inst];
         const Ctl st = *gp(I.ctl);
         const int mode = st.mode;
@@ -995,7 +1007,9 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             double tot[kNB];
             for (int q = 0; q < kNB; ++q)
                 tot[q] = ((fin[0][q] + fin[1][q]) + fin[2][q]) + fin[3][q];
-            Ctl c = *gp(I.ctl);
+            // the control block is unchanged since this work-group read it (only the last
+            // work-group of the instance writes it, below)
+            Ctl c = st;
             control(c, P, mode, tot, tot + kNC, g_red, g_grow);
             *gp(I.ctl) = c;
             __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -624,6 +624,10 @@ public:
         o.pass_bytes = bytes;
         o.pass_ms = r.pass_ms;
         o.combine_ms = r.comb_ms;
+        o.verify_retries = c.verify_fails;
+        o.kkt_estimate = c.K_cand;
+        for (int q = 0; q < 3; ++q) o.estimate_parts[q] = c.e_rel[q];
+        o.estimate_objective = c.e_obj;
         (void)I;
         r.done = true;
         arena_.release(r.off, l.bytes);
