@@ -1120,7 +1120,10 @@ ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot
     bool stop_sent = false;
     ot_status hard = OT_OK;
     while (!E.active().empty()) {
-        ot_status st = E.run_block(prm.profile ? 1 : prm.graph_slots);
+        // blocks of about 8 ms: fewer host round trips than the server's 2 ms (which
+        // bound admission latency); an instance that finishes inside a block idles for
+        // the rest of it at about 3 us per slot
+        ot_status st = E.run_block(prm.profile ? 1 : prm.graph_slots, 8.0);
         if (st != OT_OK) return st;
         std::vector<Req *> fin, stuck;
         for (Req *r : E.active()) {
