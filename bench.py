@@ -480,7 +480,8 @@ def main():
             "algorithmic_bytes_per_launch": round(avg_bytes), "launches": launches,
             "passes_by_kind": {"init": rp["mode_passes"][1], "trial": rp["mode_passes"][2],
                                "full": rp["mode_passes"][3], "restart": rp["mode_passes"][4],
-                               "verify": rp["mode_passes"][5]}}
+                               "verify": rp["mode_passes"][5], "fold": rp["mode_passes"][6],
+                               "trial_or_full_folding_two": rp["avg_fold_passes"]}}
 
     forms = {}
     if not args.no_forms:

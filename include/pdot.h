@@ -170,9 +170,11 @@ typedef struct {
     double rel_primal, rel_dual, rel_gap, rel_kkt;   /* of the returned triple     */
     double eta, omega;         /* final step size and primal weight                */
     double seconds;            /* wall time of the call                            */
-    int64_t mode_passes[6];    /* streaming passes by kind: 0 unused, 1 start-point KKT,
-                                  2 step trial, 3 average fold + KKT + trial, 4 restart
-                                  distance, 5 final verification                      */
+    int64_t mode_passes[7];    /* streaming passes by kind: 0 unused, 1 start-point KKT,
+                                  2 step trial, 3 KKT + trial, 4 restart distance,
+                                  5 final verification, 6 fold of the current iterate into
+                                  the stored average (before a restart to the average or
+                                  before returning it)                                 */
     double pass_bytes;         /* algorithmic HBM bytes of those passes (plan, average
                                   and cost streams; partial sums excluded)            */
     double pass_ms;            /* profile mode: summed duration of the pass launches   */
@@ -183,6 +185,9 @@ typedef struct {
                                   when the solver stopped (the verified value is rel_kkt) */
     double estimate_parts[3];  /* its rel_primal, rel_dual, rel_gap                        */
     double estimate_objective; /* its <C, X> (before the plan's storage rounding)          */
+    int64_t avg_fold_passes;   /* kinds 2 and 3 that also folded their start iterate and
+                                  their trial into the stored running average (the average
+                                  is read and written every other pass)                  */
 } ot_result;
 
 /* Fill *prm with the defaults described above (precision OT_PREC_FP32). */

@@ -115,7 +115,7 @@ class OtResult(ct.Structure):
         ("eta", ct.c_double),
         ("omega", ct.c_double),
         ("seconds", ct.c_double),
-        ("mode_passes", ct.c_int64 * 6),
+        ("mode_passes", ct.c_int64 * 7),
         ("pass_bytes", ct.c_double),
         ("pass_ms", ct.c_double),
         ("combine_ms", ct.c_double),
@@ -123,6 +123,7 @@ class OtResult(ct.Structure):
         ("kkt_estimate", ct.c_double),
         ("estimate_parts", ct.c_double * 3),
         ("estimate_objective", ct.c_double),
+        ("avg_fold_passes", ct.c_int64),
     ]
 
     def as_dict(self):

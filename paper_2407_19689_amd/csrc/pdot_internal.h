@@ -20,17 +20,25 @@ enum Mode : int32_t {
     M_FULL = 3,     // fold the newly accepted iterate into the average, KKT of current and
                     // average, restart/termination checks, and a speculative trial step
     M_RESTART = 4,  // distance of the restart point to the previous one (primal weight)
-    M_VERIFY = 5    // exact KKT and objective of the returned triple
+    M_VERIFY = 5,   // exact KKT and objective of the returned triple
+    M_FOLD = 6      // fold the current iterate into the stored average (before a restart
+                    // to the average, or before returning it, when the fold is pending)
 };
+constexpr int kModes = 7;
 
 enum CostKind : int32_t {
     C_STORED = 0, C_PTS_SQ = 1, C_PTS_EU = 2, C_GRID_SQ = 3, C_GRID_L1 = 4, C_GRID_L2 = 5, C_GRID_LINF = 6
 };
 constexpr bool is_grid(int c) { return c >= C_GRID_SQ && c <= C_GRID_LINF; }
 
-// Roles of the four m x ld plan buffers.  The trial buffer is never the current, the
-// average or the restart anchor, so a role swap replaces every copy.
-enum Role : int32_t { R_CUR = 0, R_TRIAL = 1, R_AVG = 2, R_ANCHOR = 3 };
+// Roles of the five m x ld plan buffers.  The trial buffer is never the current, the
+// average, the next average or the restart anchor, so a role swap replaces every copy.
+// The stored average lags: a pass that starts from an iterate not yet in the average
+// folds it and the trial it produces (both are in registers) into the next-average
+// buffer, and the pass after an accepted trial leaves the average alone, so the average
+// is read and written every other pass.
+enum Role : int32_t { R_CUR = 0, R_TRIAL = 1, R_AVG = 2, R_ANCHOR = 3, R_AVGN = 4 };
+constexpr int kBufs = 5;
 
 constexpr int kWG = 256;          // threads per work-group (4 wave64)
 constexpr int kCombEntries = 64;  // rows or columns handled by one combine work-group
@@ -41,7 +49,8 @@ constexpr int kNB = kNC + kNS;    // combine record: entry scalars, then its sha
 // scalars of the rounding passes (in combscal of the rounding instance)
 enum { RD_MARG = 0, RD_L1 = 1, RD_UPPER = 2, RD_CHANGE = 3, RD_LOWER = 4, RD_VIOL = 5 };
 
-// tile scalar slots
+// tile scalar slots (TS_AUX: ||C||_F^2 at the start point, the squared distance of the restart
+// pass, and <C, next average> in a pass that folds two iterates)
 enum { TS_DX2 = 0, TS_DRES = 1, TS_DRESB = 2, TS_POBJ = 3, TS_POBJB = 4, TS_AUX = 5 };
 // combine scalar slots
 enum { CS_PRES = 0, CS_DOBJ = 1, CS_PRESB = 2, CS_DOBJB = 3, CS_DY2 = 4, CS_INTER = 5,
@@ -60,20 +69,25 @@ struct Prm {
 // last work-group, or by the host between graph launches).
 struct Ctl {
     int32_t mode, status;
-    int32_t xr[4];          // role -> physical plan buffer
+    int32_t xr[kBufs];      // role -> physical plan buffer
     int32_t pv, pbv, rsv;   // current version of p/q, of the averaged p/q, of the sums
+    int32_t lag;            // the current iterate is not yet folded into the stored average
+    int32_t pending;        // after an M_FOLD pass: M_RESTART or M_VERIFY
     int32_t cand_avg;       // last restart candidate is the average
     int32_t ret_x, ret_avg; // returned plan buffer / returned duals are the averages
     int32_t stop;           // host request: stop at the next decision point
     int32_t verify_fails;   // final verifications that did not confirm the tolerance
     int64_t T, k, passes, restarts, kpasses;
-    int64_t mcount[6];      // slots executed per mode (index: Mode)
+    int64_t mcount[kModes]; // slots executed per mode (index: Mode)
+    int64_t fold2;          // trial passes that also folded two iterates into the average
     double eta, omega, wsum, a_fold;
     double tol_eff;         // internal termination threshold (tightened on a failed verify)
     double K_start, K_prev, K_cand;
     double norm_b, norm_c;
     double r_obj, r_dobj, r_relP, r_relD, r_relG, r_kkt;
     double e_rel[3], e_obj;  // running estimate of the candidate (rel_P, rel_D, rel_G, <C,X>)
+    double pobjb;           // <C, Xbar> of the stored average when it holds the current
+                            // iterate (computed by the pass that wrote it, before rounding)
 };
 
 struct Inst {
@@ -83,7 +97,7 @@ struct Inst {
     int32_t rows, ncb, nrb, ntiles;
     int32_t ncomb, pad0;
     double scale;
-    void *X[4];
+    void *X[kBufs];
     const void *C;          // stored cost in the working precision (C_STORED)
     const double *xs, *ys;  // coordinates (points kinds)
     const double *f, *g;

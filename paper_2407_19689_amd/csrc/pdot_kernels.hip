@@ -26,20 +26,41 @@
 
 #include "pdot_internal.h"
 
-// Rows each wave keeps in flight per loop step, for FP32 and FP64 plans.
+// Rows each wave keeps in flight per loop step, for FP32 and FP64 plans: passes that
+// stream one plan (and the cost), and passes that stream two plans (a fold into the
+// average, the restart distance).
 #ifndef PDOT_RU_F32
 #define PDOT_RU_F32 2
 #endif
 #ifndef PDOT_RU_F64
 #define PDOT_RU_F64 2
 #endif
+#ifndef PDOT_RU_F32_AVG
+#define PDOT_RU_F32_AVG 1
+#endif
+#ifndef PDOT_RU_F64_AVG
+#define PDOT_RU_F64_AVG 1
+#endif
 // Rows each wave keeps in flight in the resident kernel (one work-group per instance has
 // few waves, so each needs more rows in flight).
 #ifndef PDOT_RU_RES
 #define PDOT_RU_RES 2
 #endif
-// Row ranges of tiles are multiples of 16 rows, so a wave may keep at most 4 rows in flight.
-static_assert(PDOT_RU_F32 <= 4 && PDOT_RU_F64 <= 4 && PDOT_RU_RES <= 4, "rows in flight exceed 16-row tiles");
+// Row ranges of tiles are multiples of 16 rows and the four waves step through them 4*RU
+// rows at a time, so RU must divide 4.
+#define PDOT_RU_OK(r) ((r) == 1 || (r) == 2 || (r) == 4)
+static_assert(PDOT_RU_OK(PDOT_RU_F32) && PDOT_RU_OK(PDOT_RU_F64) && PDOT_RU_OK(PDOT_RU_F32_AVG) &&
+                  PDOT_RU_OK(PDOT_RU_F64_AVG) && PDOT_RU_OK(PDOT_RU_RES),
+              "rows in flight must divide 4");
+// Loop steps of rows whose loads are in flight while a step is computed (register sets
+// in the ring: this plus one).
+#ifndef PDOT_PF
+#define PDOT_PF 1
+#endif
+#ifndef PDOT_PF_AVG
+#define PDOT_PF_AVG 1
+#endif
+static_assert(PDOT_PF >= 1 && PDOT_PF <= 3 && PDOT_PF_AVG >= 1 && PDOT_PF_AVG <= 3, "prefetch depth 1..3");
 // Waves per SIMD the streaming kernel is compiled for (bounds its registers).
 #ifndef PDOT_PASS_WAVES
 #define PDOT_PASS_WAVES 2
@@ -261,17 +282,27 @@ __device__ __forceinline__ double row_dual(const PDOT_GLOBAL double *p, int64_t 
 // is 0 and no residual term is positive, so padding contributes exactly zero without a
 // masked code path.  Plan padding is zero and stays zero.  Per-row quantities (row base,
 // duals, pixel coordinates, hash) are wave-uniform and live in scalar registers.
-template <typename TX, int VEC, int COST, int MODE, bool RES = false>
+// F2 (trial and full passes whose start iterate is not yet in the stored average): fold
+// the start iterate and then the trial into the average, in FP64 registers, and store the
+// result (the average after the trial, should it be accepted) in the next-average buffer;
+// the two folds are the sequential ones, so an FP64 plan gets exactly the running average.
+template <typename TX, int VEC, int COST, int MODE, bool RES = false, bool F2 = false>
 __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &tl, double *lds)
 {
     // Every product and sum below is rounded as written (fused multiply-adds only where
     // fma() is spelled out), so all kernel variants (cost source, tile shape) round alike.
 #pragma clang fp contract(off)
-    constexpr int RU = RES ? PDOT_RU_RES : (sizeof(TX) == 4 ? PDOT_RU_F32 : PDOT_RU_F64);   // rows in flight per wave
     constexpr bool kX = MODE != M_INIT;         // reads the plan
-    constexpr bool kCost = MODE != M_RESTART;   // needs C
+    constexpr bool kCost = MODE != M_RESTART && MODE != M_FOLD;   // needs C
     constexpr bool kTrial = MODE == M_TRIAL || MODE == M_FULL;
-    constexpr bool kFold = MODE == M_FULL;
+    constexpr bool kFold2 = kTrial && F2;                  // folds two iterates
+    constexpr bool kAvgIn = kFold2 || MODE == M_FOLD;      // reads the stored average
+    constexpr bool kTwo = kAvgIn || MODE == M_RESTART;    // streams two plans
+    constexpr int RU = RES ? PDOT_RU_RES
+                           : (sizeof(TX) == 4 ? (kTwo ? PDOT_RU_F32_AVG : PDOT_RU_F32)
+                                              : (kTwo ? PDOT_RU_F64_AVG : PDOT_RU_F64));   // rows in flight per wave
+    constexpr bool kAvgOut = kAvgIn;                       // writes the next average
+    constexpr bool kAvgKKT = MODE == M_FULL;               // KKT pieces of the average
     constexpr bool kRowCol = kTrial || MODE == M_VERIFY;
     constexpr bool kGrid = is_grid(COST);
     constexpr bool kPts = COST == C_PTS_SQ || COST == C_PTS_EU;
@@ -291,7 +322,8 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
     const int xc = (MODE == M_VERIFY) ? st.ret_x : st.xr[R_CUR];
     const PDOT_GLOBAL TX *__restrict__ Xc = gp((const TX *)I.X[xc]);
     PDOT_GLOBAL TX *__restrict__ Xt = gp((TX *)I.X[st.xr[R_TRIAL]]);
-    PDOT_GLOBAL TX *__restrict__ Xb = gp((TX *)I.X[st.xr[R_AVG]]);
+    const PDOT_GLOBAL TX *__restrict__ Xb = gp((const TX *)I.X[st.xr[R_AVG]]);
+    PDOT_GLOBAL TX *__restrict__ Xn = gp((TX *)I.X[st.xr[R_AVGN]]);
     const PDOT_GLOBAL TX *__restrict__ Xa = gp((const TX *)I.X[st.xr[R_ANCHOR]]);
     const PDOT_GLOBAL TX *__restrict__ Cs = gp((const TX *)I.C);
     const bool use_avg_duals = (MODE == M_VERIFY) && st.ret_avg;
@@ -304,8 +336,11 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
     PDOT_GLOBAL double *__restrict__ rowpart = gp(I.rowpart);
     PDOT_GLOBAL double *__restrict__ colpart = gp(I.colpart);
     const double tau = st.eta / st.omega;
-    const double a = st.a_fold;
+    const double a = st.a_fold;   // weight of the start iterate in the average
     const bool first_fold = st.k == 1;
+    // weight of the trial in the average, as the control computes it on acceptance
+    const double wt = I.prm.avg_weighting == 1 ? 1.0 : st.eta;
+    const double a2 = wt / (st.wsum + wt);
     const uint32_t hiter = mix32((uint32_t)st.T * 0x85EBCA77U + 0x27D4EB2FU);
     const double scale = I.scale;
     const float scale32 = (float)I.scale;
@@ -325,7 +360,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
         colok[v] = ok;
         hcol[v] = mix32((uint32_t)j * 0x9E3779B9U + 0x632BE5ABU);
         qv[v] = ok ? qc[jc] : kNegInf;
-        qbv[v] = (ok && kFold) ? qbc[jc] : kNegInf;
+        qbv[v] = (ok && kAvgKKT) ? qbc[jc] : kNegInf;
         gja[v] = gjb[v] = 0.0f;
         yc[v][0] = yc[v][1] = yc[v][2] = 0.0;
         if constexpr (kGrid) {
@@ -368,7 +403,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
             const int64_t ic = rok ? i : m - 1;
             const int64_t rowoff = i * ld + jband;   // uniform row base; lanes add jl
             R.pi[u] = rok ? row_dual<RES>(pc, i) : kNegInf;
-            R.pbi[u] = (rok && kFold) ? row_dual<RES>(pbc, i) : kNegInf;
+            R.pbi[u] = (rok && kAvgKKT) ? row_dual<RES>(pbc, i) : kNegInf;
             R.gia[u] = (float)ga;
             R.gib[u] = (float)gb;
             if constexpr (kGrid) {
@@ -389,7 +424,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
             if (active) {
                 if constexpr (kX) load_pack<TX, VEC>(Xc + rowoff + jl, R.x[u]);
                 if constexpr (kCost && COST == C_STORED) load_pack<TX, VEC>(Cs + rowoff + jl, R.c[u]);
-                if constexpr (kFold) load_pack<TX, VEC>(Xb + rowoff + jl, R.b[u]);
+                if constexpr (kAvgIn) load_pack<TX, VEC>(Xb + rowoff + jl, R.b[u]);
                 if constexpr (MODE == M_RESTART) load_pack<TX, VEC>(Xa + rowoff + jl, R.an[u]);
             }
         }
@@ -437,24 +472,29 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                     rsum[u] += xd;
                     csv[v] += xd;
                 }
+                // fold of the start iterate into the running average
+                double xbn = 0.0;
+                if constexpr (kAvgIn) {
+                    const double xbd = (double)R.b[u][v];
+                    xbn = first_fold ? xd : fma(a, xd, (1.0 - a) * xbd);
+                }
+                if constexpr (MODE == M_FOLD) xb_out[v] = store_avg<TX>(xbn, hrow ^ hcol[v]);
                 if constexpr (kTrial) {
                     const double sg = R.pi[u] + qv[v];
                     const double gr = cd - sg;                // G_ij = C_ij - p_i - q_j
-                    if constexpr (kFold) {
-                        // KKT pieces of the current iterate (its duals are p, q)
+                    if constexpr (kAvgKKT) {
+                        // KKT pieces of the current iterate (its duals are p, q) and of the
+                        // average (averaged duals); the averaged objective uses the value
+                        // before storage rounding, like the averaged row and column sums
+                        // (the final verification measures the stored arrays).  Without F2
+                        // the average already holds the current iterate and its objective
+                        // came from the pass that wrote it.
                         const double ng = fmin(gr, 0.0);
                         s_dres = fma(ng, ng, s_dres);
                         s_pobj = fma(cd, xd, s_pobj);
-                        // fold the current iterate into the running average; the averaged
-                        // objective uses the value before storage rounding, like the
-                        // averaged row and column sums (the final verification measures the
-                        // stored arrays)
-                        const double xbd = (double)R.b[u][v];
-                        const double xbn = first_fold ? xd : fma(a, xd, (1.0 - a) * xbd);
-                        xb_out[v] = store_avg<TX>(xbn, hrow ^ hcol[v]);
                         const double nb = fmax((R.pbi[u] + qbv[v]) - cd, 0.0);
                         s_dresb = fma(nb, nb, s_dresb);
-                        s_pobjb = fma(cd, xbn, s_pobjb);
+                        if constexpr (kFold2) s_pobjb = fma(cd, xbn, s_pobjb);
                     }
                     const double y = fma(-tau, gr, xd);
                     const TX xn = (TX)fmax(y, 0.0);
@@ -464,12 +504,18 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                     rsum[u] += xnd;
                     csv[v] += xnd;
                     s_dx2 = fma(d, d, s_dx2);
+                    if constexpr (kFold2) {
+                        // second fold: the trial as stored, with its own weight
+                        const double xbt = fma(a2, xnd, (1.0 - a2) * xbn);
+                        xb_out[v] = store_avg<TX>(xbt, hrow ^ hcol[v]);
+                        s_aux = fma(cd, xbt, s_aux);
+                    }
                 }
             }
             if (active) {
                 const int64_t rowoff = i * ld + jband;
                 if constexpr (kTrial) store_pack_nt<TX, VEC>(Xt + rowoff + jl, xn_out);
-                if constexpr (kFold) store_pack_nt<TX, VEC>(Xb + rowoff + jl, xb_out);
+                if constexpr (kAvgOut) store_pack_nt<TX, VEC>(Xn + rowoff + jl, xb_out);
             }
             // keep one row's arithmetic together: bounds the live temporaries
             __builtin_amdgcn_sched_barrier(0);
@@ -484,22 +530,26 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
         }
     };
 
-    // Software pipeline: the loads of the next RU rows are issued before the arithmetic
-    // of the current ones, alternating between two register sets.
+    // Software pipeline: the loads of the next PF steps of RU rows are in flight while a
+    // step is computed, in a ring of PF + 1 register sets (the ring loop is unrolled, so
+    // every set index is a constant).
+    constexpr int PF = RES ? 1 : (kTwo ? PDOT_PF_AVG : PDOT_PF);
+    constexpr int NS = PF + 1;
     const int64_t step = 4 * RU;
-    Rows A, B;
+    Rows S[NS];
     int64_t ib = i0 + wave;
-    if (ib < ie) load_rows(ib, A);
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+        if (ib + s * step < ie) load_rows(ib + s * step, S[s]);
     while (ib < ie) {
-        if (ib + step < ie) load_rows(ib + step, B);
-        __builtin_amdgcn_sched_barrier(0);
-        compute_rows(ib, A);
-        ib += step;
-        if (ib >= ie) break;
-        if (ib + step < ie) load_rows(ib + step, A);
-        __builtin_amdgcn_sched_barrier(0);
-        compute_rows(ib, B);
-        ib += step;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (ib + PF * step < ie) load_rows(ib + PF * step, S[(s + PF) % NS]);
+            __builtin_amdgcn_sched_barrier(0);
+            compute_rows(ib, S[s]);
+            ib += step;
+            if (ib >= ie) break;
+        }
     }
 
     // column partials: combine the four waves in a fixed order
@@ -560,10 +610,17 @@ void k_pass(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
         const Ctl st = *cp((const Ctl *)I.ctl);
         switch (st.mode) {
         case M_INIT: tile_body<TX, VEC, COST, M_INIT>(I, st, tl, lds); break;
-        case M_TRIAL: tile_body<TX, VEC, COST, M_TRIAL>(I, st, tl, lds); break;
-        case M_FULL: tile_body<TX, VEC, COST, M_FULL>(I, st, tl, lds); break;
+        case M_TRIAL:
+            if (st.lag) tile_body<TX, VEC, COST, M_TRIAL, false, true>(I, st, tl, lds);
+            else tile_body<TX, VEC, COST, M_TRIAL>(I, st, tl, lds);
+            break;
+        case M_FULL:
+            if (st.lag) tile_body<TX, VEC, COST, M_FULL, false, true>(I, st, tl, lds);
+            else tile_body<TX, VEC, COST, M_FULL>(I, st, tl, lds);
+            break;
         case M_RESTART: tile_body<TX, VEC, COST, M_RESTART>(I, st, tl, lds); break;
         case M_VERIFY: tile_body<TX, VEC, COST, M_VERIFY>(I, st, tl, lds); break;
+        case M_FOLD: tile_body<TX, VEC, COST, M_FOLD>(I, st, tl, lds); break;
         default: break;
         }
     }
@@ -602,8 +659,20 @@ __device__ __forceinline__ void finish(Ctl &c, const Prm &P, int status)
 {
     c.status = status;
     c.ret_avg = (P.output == 0 && c.cand_avg && c.T > 0 && c.k > 0) ? 1 : 0;
+    if (c.ret_avg && c.lag) {   // the average does not hold the current iterate yet
+        c.pending = M_VERIFY;
+        c.mode = M_FOLD;
+        return;
+    }
     c.ret_x = c.ret_avg ? c.xr[R_AVG] : c.xr[R_CUR];
     c.mode = M_VERIFY;
+}
+
+__device__ __forceinline__ void swap_avg(Ctl &c)
+{
+    const int t = c.xr[R_AVG];
+    c.xr[R_AVG] = c.xr[R_AVGN];
+    c.xr[R_AVGN] = t;
 }
 
 __device__ __forceinline__ bool limits_hit(const Ctl &c, const Prm &P)
@@ -614,8 +683,9 @@ __device__ __forceinline__ bool limits_hit(const Ctl &c, const Prm &P)
 // Step-size check of the trial (Section 5, adaptive step size).
 // g_red = (T+1)^-a and g_grow = (T+1)^-b are evaluated by the caller (in parallel with
 // its loads) for the current T.
+// aux: <C, next average> of a pass that folded two iterates.
 __device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double inter,
-                            double g_red, double g_grow)
+                            double aux, double g_red, double g_grow)
 {
     c.passes += 1;
     const double eta_used = c.eta;
@@ -635,12 +705,21 @@ __device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, do
         }
     }
     if (accept) {
+        if (c.lag) {
+            // the pass folded the current iterate and the trial: the next average is the
+            // average of the new current iterate
+            swap_avg(c);
+            c.pobjb = aux;
+            c.lag = 0;
+        } else {
+            c.lag = 1;
+        }
         const int old_cur = c.xr[R_CUR];
         const int new_cur = c.xr[R_TRIAL];
         int nt = old_cur;
         if (old_cur == c.xr[R_ANCHOR]) {
-            for (int b = 0; b < 4; ++b)
-                if (b != new_cur && b != c.xr[R_AVG] && b != c.xr[R_ANCHOR]) nt = b;
+            for (int b = 0; b < kBufs; ++b)
+                if (b != new_cur && b != c.xr[R_AVG] && b != c.xr[R_AVGN] && b != c.xr[R_ANCHOR]) nt = b;
         }
         c.xr[R_CUR] = new_cur;
         c.xr[R_TRIAL] = nt;
@@ -662,6 +741,8 @@ __device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, do
 __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const double *ts,
                         double g_red, double g_grow)
 {
+    // constant indices only: an array of the control block indexed at run time would put
+    // the whole block in scratch memory
     c.kpasses += 1;
     switch (mode) {
     case M_INIT: c.mcount[M_INIT] += 1; break;
@@ -669,8 +750,10 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
     case M_FULL: c.mcount[M_FULL] += 1; break;
     case M_RESTART: c.mcount[M_RESTART] += 1; break;
     case M_VERIFY: c.mcount[M_VERIFY] += 1; break;
+    case M_FOLD: c.mcount[M_FOLD] += 1; break;
     default: break;
     }
+    if ((mode == M_TRIAL || mode == M_FULL) && c.lag) c.fold2 += 1;
     if (mode == M_INIT) {
         c.norm_b = sqrt(cs[CS_AUX]);
         c.norm_c = sqrt(ts[TS_AUX]);
@@ -690,19 +773,22 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
         return;
     }
     if (mode == M_TRIAL) {
-        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], g_red, g_grow);
+        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], ts[TS_AUX], g_red, g_grow);
         return;
     }
     if (mode == M_FULL) {
         double ec[3], ea[3];
         const double kc = rel_kkt(P, c.norm_b, c.norm_c, cs[CS_PRES], ts[TS_DRES], ts[TS_POBJ],
                                   cs[CS_DOBJ], ec);
+        // <C, average>: from this pass when it folded the current iterate, else from the
+        // pass that wrote the stored average
+        const double pobjb = c.lag ? ts[TS_POBJB] : c.pobjb;
         const double ka = rel_kkt(P, c.norm_b, c.norm_c, cs[CS_PRESB], ts[TS_DRESB],
-                                  ts[TS_POBJB], cs[CS_DOBJB], ea);
+                                  pobjb, cs[CS_DOBJB], ea);
         // restart candidate (Section 5): the current iterate only if strictly better
         c.cand_avg = !(kc < ka);
         for (int q = 0; q < 3; ++q) c.e_rel[q] = c.cand_avg ? ea[q] : ec[q];
-        c.e_obj = c.cand_avg ? ts[TS_POBJB] : ts[TS_POBJ];
+        c.e_obj = c.cand_avg ? pobjb : ts[TS_POBJ];
         double K = c.cand_avg ? ka : kc;
         if (!(K == K)) {
             c.status = ST_NUMERIC;
@@ -728,9 +814,14 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
             }
         }
         if (restart) {
-            if (c.cand_avg) c.xr[R_CUR] = c.xr[R_AVG];
             c.K_start = K;
             c.K_prev = K;
+            if (c.cand_avg && c.lag) {   // materialise the average first
+                c.pending = M_RESTART;
+                c.mode = M_FOLD;
+                return;
+            }
+            if (c.cand_avg) c.xr[R_CUR] = c.xr[R_AVG];
             c.mode = M_RESTART;
             return;
         }
@@ -739,7 +830,19 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
             finish(c, P, ST_NOT_CONVERGED);
             return;
         }
-        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], g_red, g_grow);
+        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], ts[TS_AUX], g_red, g_grow);
+        return;
+    }
+    if (mode == M_FOLD) {
+        swap_avg(c);
+        c.lag = 0;
+        if (c.pending == M_RESTART) {
+            c.xr[R_CUR] = c.xr[R_AVG];
+            c.mode = M_RESTART;
+        } else {
+            c.ret_x = c.xr[R_AVG];
+            c.mode = M_VERIFY;
+        }
         return;
     }
     if (mode == M_RESTART) {
@@ -750,9 +853,19 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
             c.omega = exp(P.theta * log(dY / dX) + (1.0 - P.theta) * log(c.omega));
         const int cur = c.xr[R_CUR];
         c.xr[R_ANCHOR] = cur;
-        // the two lowest buffer indices other than the restart point
-        c.xr[R_TRIAL] = cur == 0 ? 1 : 0;
-        c.xr[R_AVG] = cur <= 1 ? 2 : 1;
+        // the three lowest buffer indices other than the restart point, in role order
+        int o0 = -1, o1 = -1, o2 = -1;
+#pragma unroll
+        for (int b = kBufs - 1; b >= 0; --b)
+            if (b != cur) {
+                o2 = o1;
+                o1 = o0;
+                o0 = b;
+            }
+        c.xr[R_TRIAL] = o0;
+        c.xr[R_AVG] = o1;
+        c.xr[R_AVGN] = o2;
+        c.lag = 0;
         c.wsum = 0.0;
         c.k = 0;
         c.restarts += 1;
@@ -802,7 +915,7 @@ __device__ __forceinline__ IndexIn index_load(const PDOT_CONST Inst &I, const Ct
 {
     IndexIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     in.fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
-    if (mode == M_INIT) return in;
+    if (mode == M_INIT || mode == M_FOLD) return in;
     in.pc0 = gp(rows ? I.p[st.pv] : I.q[st.pv])[idx];
     in.pb0 = gp(rows ? I.pb[st.pbv] : I.qb[st.pbv])[idx];
     in.rc0 = gp(rows ? I.rs[st.rsv] : I.cs[st.rsv])[idx];
@@ -1036,10 +1149,17 @@ __device__ void resident_pass(const PDOT_CONST Inst &I, const Ctl &st, int slot,
         const Tile tl{slot, 0, cb, cb};
         switch (st.mode) {
         case M_INIT: tile_body<TX, VEC, COST, M_INIT, true>(I, st, tl, lds); break;
-        case M_TRIAL: tile_body<TX, VEC, COST, M_TRIAL, true>(I, st, tl, lds); break;
-        case M_FULL: tile_body<TX, VEC, COST, M_FULL, true>(I, st, tl, lds); break;
+        case M_TRIAL:
+            if (st.lag) tile_body<TX, VEC, COST, M_TRIAL, true, true>(I, st, tl, lds);
+            else tile_body<TX, VEC, COST, M_TRIAL, true>(I, st, tl, lds);
+            break;
+        case M_FULL:
+            if (st.lag) tile_body<TX, VEC, COST, M_FULL, true, true>(I, st, tl, lds);
+            else tile_body<TX, VEC, COST, M_FULL, true>(I, st, tl, lds);
+            break;
         case M_RESTART: tile_body<TX, VEC, COST, M_RESTART, true>(I, st, tl, lds); break;
         case M_VERIFY: tile_body<TX, VEC, COST, M_VERIFY, true>(I, st, tl, lds); break;
+        case M_FOLD: tile_body<TX, VEC, COST, M_FOLD, true>(I, st, tl, lds); break;
         default: break;
         }
     }

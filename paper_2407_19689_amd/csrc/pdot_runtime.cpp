@@ -50,8 +50,8 @@ hipError_t launch_widen(const float *src, int64_t m, int64_t n, double *dst, int
 
 using namespace pdot;
 
-static_assert(OT_COST_GRID_SQEUCLID == C_GRID_SQ && OT_COST_GRID_L1 == C_GRID_L1 &&
-                  OT_COST_GRID_L2 == C_GRID_L2 && OT_COST_GRID_LINF == C_GRID_LINF,
+static_assert((int)OT_COST_GRID_SQEUCLID == (int)C_GRID_SQ && (int)OT_COST_GRID_L1 == (int)C_GRID_L1 &&
+                  (int)OT_COST_GRID_L2 == (int)C_GRID_L2 && (int)OT_COST_GRID_LINF == (int)C_GRID_LINF,
               "grid cost kinds share their numbering with the kernels");
 
 namespace {
@@ -115,7 +115,7 @@ struct Layout {
     bool resident = false;    // one work-group runs the whole instance
     int lane = 0;             // size lane (instances on the whole GPU)
     size_t es = 4;
-    size_t off_X[4] = {0, 0, 0, 0}, off_C = 0, off_xs = 0, off_ys = 0, off_f = 0, off_g = 0;
+    size_t off_X[kBufs] = {}, off_C = 0, off_xs = 0, off_ys = 0, off_f = 0, off_g = 0;
     size_t off_rowv = 0, off_colv = 0, off_rowpart = 0, off_colpart = 0;
     size_t off_tiles = 0, off_comb = 0, off_counter = 0, off_ctl = 0;
     size_t bytes = 0;
@@ -217,7 +217,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
         return o;
     };
     const size_t mat = (size_t)L.m_alloc * (size_t)L.ld * L.es;
-    for (int b = 0; b < 4; ++b) L.off_X[b] = take(mat);
+    for (int b = 0; b < kBufs; ++b) L.off_X[b] = take(mat);
     L.off_C = L.stored ? take(mat) : 0;
     L.off_xs = L.dim ? take(sizeof(double) * (size_t)L.m * L.dim) : 0;
     L.off_ys = L.dim ? take(sizeof(double) * (size_t)L.n * L.dim) : 0;
@@ -610,17 +610,19 @@ public:
         o.eta = c.eta;
         o.omega = c.omega;
         // algorithmic bytes per element of each pass kind (plan element size b, cost
-        // element size bc, 0 when regenerated): start-point KKT reads C; a trial reads X
-        // and C and writes X+; the full pass also reads and writes the average; the
-        // restart pass reads two plans; verification reads X and C
+        // element size bc, 0 when regenerated): start-point KKT reads C; a trial or full
+        // pass reads X and C and writes X+, and when it folds two iterates it also reads
+        // the average and writes the next one; the restart pass reads two plans;
+        // verification reads X and C; the fold pass reads two plans and writes one
         const double b = (double)l.es, bc = l.stored ? (double)l.es : 0.0;
-        const double per[6] = {0.0, bc, 2 * b + bc, 4 * b + bc, 2 * b, b + bc};
+        const double per[kModes] = {0.0, bc, 2 * b + bc, 2 * b + bc, 2 * b, b + bc, 3 * b};
         const double elems = (double)l.m * (double)l.n;
-        double bytes = 0.0;
-        for (int k = 0; k < 6; ++k) {
+        double bytes = 2 * b * elems * (double)c.fold2;
+        for (int k = 0; k < kModes; ++k) {
             o.mode_passes[k] = c.mcount[k];
             bytes += per[k] * elems * (double)c.mcount[k];
         }
+        o.avg_fold_passes = c.fold2;
         o.pass_bytes = bytes;
         o.pass_ms = r.pass_ms;
         o.combine_ms = r.comb_ms;
@@ -770,7 +772,7 @@ private:
         I.ntiles = l.ntiles;
         I.ncomb = l.ncomb;
         I.scale = pb.cost.scale;
-        for (int k = 0; k < 4; ++k) I.X[k] = b + l.off_X[k];
+        for (int k = 0; k < kBufs; ++k) I.X[k] = b + l.off_X[k];
         I.C = l.stored ? (const void *)(b + l.off_C) : nullptr;
         I.xs = l.dim ? (const double *)(b + l.off_xs) : nullptr;
         I.ys = l.dim ? (const double *)(b + l.off_ys) : nullptr;
@@ -835,7 +837,7 @@ private:
         memset(&c, 0, sizeof(c));
         c.mode = M_INIT;
         c.status = ST_RUNNING;
-        for (int k = 0; k < 4; ++k) c.xr[k] = k;
+        for (int k = 0; k < kBufs; ++k) c.xr[k] = k;
         c.eta = prm_.eta0 > 0.0 ? prm_.eta0 : 1.0 / std::sqrt((double)(m + n));
         c.omega = prm_.omega0 > 0.0 ? prm_.omega0 : 1.0;
         c.tol_eff = r.tol;
