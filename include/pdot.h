@@ -142,8 +142,9 @@ typedef struct {
     double step_reduction_exp, step_growth_exp;
     int32_t tile_vec;         /* columns per lane (1, 2, 4), 0 = autotuned    */
     int32_t tile_rows;        /* rows per tile (multiple of 16), 0 = autotuned */
-    int32_t profile;          /* 1: launch slots one by one (no graph) and time every
-                                 launch with HIP events (ot_result.pass_ms, combine_ms) */
+    int32_t profile;          /* 1: launch blocks of 16 slots back to back without a
+                                 graph, every launch stamping its own HIP events
+                                 (ot_result.pass_ms, combine_ms)                     */
     int32_t engine;           /* 0 auto: instances of at most OT_RESIDENT_MAX_ELEMS plan
                                  entries run resident (one work-group runs the whole
                                  instance for many iterations per launch), larger ones on

@@ -68,6 +68,9 @@ static_assert(PDOT_PF >= 1 && PDOT_PF <= 3 && PDOT_PF_AVG >= 1 && PDOT_PF_AVG <=
 #ifndef PDOT_NT_STORES
 #define PDOT_NT_STORES 1
 #endif
+#ifndef PDOT_NT_LOADS
+#define PDOT_NT_LOADS 1
+#endif
 
 namespace pdot {
 
@@ -262,6 +265,31 @@ __device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, con
     }
 }
 
+// Non-temporal vector load of VEC plan entries: in the trial and fold passes the plan and
+// the average are read for the last time (the next pass reads what this one writes).
+template <typename T, int N>
+__device__ __forceinline__ void load_pack_nt(const PDOT_GLOBAL T *__restrict__ p, T (&o)[N])
+{
+    if constexpr (!PDOT_NT_LOADS) {
+        load_pack<T, N>(p, o);
+    } else {
+        constexpr int B = sizeof(T) * N < 16 ? (int)sizeof(T) * N : 16;   // bytes per piece
+        constexpr int E = B / (int)sizeof(T);                            // entries per piece
+        if constexpr (E == 1) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) o[e] = __builtin_nontemporal_load(p + e);
+        } else {
+            typedef T V __attribute__((ext_vector_type(E)));
+#pragma unroll
+            for (int c = 0; c < N / E; ++c) {
+                const V v = __builtin_nontemporal_load(reinterpret_cast<const PDOT_GLOBAL V *>(p) + c);
+#pragma unroll
+                for (int e = 0; e < E; ++e) o[c * E + e] = v[e];
+            }
+        }
+    }
+}
+
 // Per-row dual of the streaming pass.  In the resident kernel the duals are rewritten by
 // other threads of the same work-group between passes, so they are read with vector
 // loads (a workgroup-scope atomic load is never turned into a scalar-cache load); in the
@@ -422,9 +450,12 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
 #pragma unroll
             for (int v = 0; v < VEC; ++v) R.x[u][v] = R.c[u][v] = R.b[u][v] = R.an[u][v] = (TX)0;
             if (active) {
-                if constexpr (kX) load_pack<TX, VEC>(Xc + rowoff + jl, R.x[u]);
+                if constexpr (kX) {
+                    if constexpr (kTrial || MODE == M_FOLD) load_pack_nt<TX, VEC>(Xc + rowoff + jl, R.x[u]);
+                    else load_pack<TX, VEC>(Xc + rowoff + jl, R.x[u]);
+                }
                 if constexpr (kCost && COST == C_STORED) load_pack<TX, VEC>(Cs + rowoff + jl, R.c[u]);
-                if constexpr (kAvgIn) load_pack<TX, VEC>(Xb + rowoff + jl, R.b[u]);
+                if constexpr (kAvgIn) load_pack_nt<TX, VEC>(Xb + rowoff + jl, R.b[u]);
                 if constexpr (MODE == M_RESTART) load_pack<TX, VEC>(Xa + rowoff + jl, R.an[u]);
             }
         }

@@ -495,31 +495,52 @@ public:
                     if (r->L.resident && r->L.fp32 == g.fp32 && r->L.vec == g.vec && r->L.cost == g.cost)
                         r->pass_ms += t;
             }
+            // the slots of a lane are launched back to back (as in a graph block), every
+            // launch stamping its own pair of events; after the block, slot k's times go to
+            // the instances whose pass count grew by more than k (an instance stays idle
+            // once it has finished)
             for (int l = 0; l < kLanes; ++l) {
                 Lane &ln = lanes_[l];
-                for (int k = 0; k < ln.slots && ln.active; ++k) {
-                    float a = 0.f, b = 0.f;
+                if (!ln.active) continue;
+                const size_t per_slot = ln.groups.size() + 1;
+                const size_t need = 2 * per_slot * (size_t)ln.slots;
+                while (prof_ev_.size() < need) {
+                    hipEvent_t e = nullptr;
+                    HIP_TRY(hipEventCreate(&e));
+                    prof_ev_.push_back(e);
+                }
+                std::vector<int64_t> kp0(active_.size());
+                for (size_t q = 0; q < active_.size(); ++q) kp0[q] = h_ctl_[active_[q]->slot].kpasses;
+                for (int k = 0; k < ln.slots; ++k) {
+                    hipEvent_t *ev = &prof_ev_[2 * per_slot * (size_t)k];
                     for (size_t gi = 0; gi < ln.groups.size(); ++gi) {
                         const Group &g = ln.groups[gi];
                         HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln) + g.first,
-                                            d_counts() + l * kLaneCounts + gi, g.grid, s_, ev_[0], ev_[1]));
-                        HIP_TRY(hipEventSynchronize(ev_[1]));
-                        float t = 0.f;
-                        HIP_TRY(hipEventElapsedTime(&t, ev_[0], ev_[1]));
-                        a += t;
+                                            d_counts() + l * kLaneCounts + gi, g.grid, ln.s, ev[2 * gi],
+                                            ev[2 * gi + 1]));
                     }
                     HIP_TRY(launch_combine(d_insts(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups,
-                                           ln.comb_grid, s_, ev_[0], ev_[1]));
-                    HIP_TRY(hipEventSynchronize(ev_[1]));
-                    HIP_TRY(hipEventElapsedTime(&b, ev_[0], ev_[1]));
-                    for (Req *r : active_)
-                        if (!r->L.resident && r->L.lane == l && h_ctl_[r->slot].mode != M_IDLE) {
+                                           ln.comb_grid, ln.s, ev[2 * (per_slot - 1)], ev[2 * per_slot - 1]));
+                }
+                HIP_TRY(hipStreamSynchronize(ln.s));
+                for (Req *r : active_)
+                    HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
+                HIP_TRY(hipStreamSynchronize(s_));
+                for (int k = 0; k < ln.slots; ++k) {
+                    hipEvent_t *ev = &prof_ev_[2 * per_slot * (size_t)k];
+                    float a = 0.f, b = 0.f, t = 0.f;
+                    for (size_t gi = 0; gi < ln.groups.size(); ++gi) {
+                        HIP_TRY(hipEventElapsedTime(&t, ev[2 * gi], ev[2 * gi + 1]));
+                        a += t;
+                    }
+                    HIP_TRY(hipEventElapsedTime(&b, ev[2 * (per_slot - 1)], ev[2 * per_slot - 1]));
+                    for (size_t q = 0; q < active_.size(); ++q) {
+                        Req *r = active_[q];
+                        if (!r->L.resident && r->L.lane == l && h_ctl_[r->slot].kpasses - kp0[q] > k) {
                             r->pass_ms += a;
                             r->comb_ms += b;
                         }
-                    for (Req *r : active_)
-                        HIP_TRY(hipMemcpyAsync(&h_ctl_[r->slot], r->I.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s_));
-                    HIP_TRY(hipStreamSynchronize(s_));
+                    }
                 }
             }
         } else {
@@ -692,6 +713,8 @@ public:
             if (e) (void)hipEventDestroy(e);
             e = nullptr;
         }
+        for (auto &e : prof_ev_) (void)hipEventDestroy(e);
+        prof_ev_.clear();
         if (h_ctl_) (void)hipHostFree(h_ctl_);
         if (h_counts_) (void)hipHostFree(h_counts_);
         h_ctl_ = nullptr;
@@ -1042,6 +1065,7 @@ private:
     Ctl *h_ctl_ = nullptr;
     int32_t *h_counts_ = nullptr;
     hipEvent_t ev_[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> prof_ev_;   // profile mode: a start and an end event per launch
     int64_t launches_ = 0;
 };
 
@@ -1125,7 +1149,8 @@ ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot
         // blocks of about 8 ms: fewer host round trips than the server's 2 ms (which
         // bound admission latency); an instance that finishes inside a block idles for
         // the rest of it at about 3 us per slot
-        ot_status st = E.run_block(prm.profile ? 1 : prm.graph_slots, 8.0);
+        // profile mode launches blocks of 16 slots back to back without a graph
+        ot_status st = E.run_block(prm.profile ? 16 : prm.graph_slots, 8.0);
         if (st != OT_OK) return st;
         std::vector<Req *> fin, stuck;
         for (Req *r : E.active()) {

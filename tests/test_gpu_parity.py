@@ -505,6 +505,26 @@ def test_repeated_solves_are_bit_identical():
 
 
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_profile_mode_solves_like_graph_mode_and_times_every_pass(prec):
+    # profile mode launches the same kernels without a graph: identical iterates, and the
+    # event-timed launches are those of the solve (counted by kind, fold passes included)
+    inst = gen.grid_pair(46, 32, tol=1e-6)
+    a = P.solve_instance(inst, P.params(tol=1e-6, precision=prec))
+    b = P.solve_instance(inst, P.params(tol=1e-6, precision=prec, profile=1))
+    assert a[0] == P.OT_OK and b[0] == P.OT_OK
+    assert a[1]["iterations"] == b[1]["iterations"] and a[1]["restarts"] == b[1]["restarts"]
+    assert np.array_equal(a[2]["X"].cpu().numpy(), b[2]["X"].cpu().numpy())
+    r = b[1]
+    assert sum(r["mode_passes"]) == r["kernel_passes"]
+    assert r["pass_ms"] > 0.0 and r["combine_ms"] > 0.0
+    # each timed pass lasts at least a microsecond and on average well under a millisecond
+    assert 1e-3 * r["kernel_passes"] < r["pass_ms"] < 1.0 * r["kernel_passes"]
+    # passes that fold two iterates are trial or full passes, about every other one
+    full_trial = r["mode_passes"][2] + r["mode_passes"][3]
+    assert 0.3 * full_trial < r["avg_fold_passes"] <= full_trial
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
 def test_batch_equals_solo(prec):
     insts = [gen.gmm_euclid(40 + i, m, n, tol=1e-5)
              for i, (m, n) in enumerate([(33, 700), (512, 48), (260, 260), (1, 90), (97, 1)])]
