@@ -117,19 +117,41 @@ def test_fixed_step_trajectory_matches_oracle(prec, m, n, vec, rows, engine):
 
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
-def test_average_and_candidate_match_oracle(prec, engine):
+@pytest.mark.parametrize("omega,iters,avg", [(0.8, 25, 0), (10.0, 24, 1), (10.0, 25, 1)])
+def test_average_and_candidate_match_oracle(prec, engine, omega, iters, avg):
     """With output = 0 the returned plan is the restart candidate: the running average when
     its KKT error is not larger (Section 5).  Same candidate and same average as the
-    oracle (fixed step, no restart, 25 iterations)."""
+    oracle (fixed step, no restart).  The stored average lags by one iterate after an odd
+    number of accepted steps, so an average returned after 25 iterations goes through a
+    fold pass and one returned after 24 does not."""
     C, f, g = random_problem(7, 45, 77)
-    common = dict(tol=1e-12, max_iters=25, step_rule=1, restart_rule=2, output=0,
-                  eta0=0.6 / np.sqrt(122), omega0=0.8)
+    common = dict(tol=1e-12, max_iters=iters, step_rule=1, restart_rule=2, output=0,
+                  eta0=0.6 / np.sqrt(122), omega0=omega)
     Xo, po, qo, ro, _ = oracle.solve(C, f, g, **common)
     st, res, X, u, v = run_dense(C, f, g, prec, engine=engine, **common)
-    assert res["returned_average"] == ro["returned_average"]
+    assert res["returned_average"] == ro["returned_average"] == avg
+    assert res["mode_passes"][6] == avg * (iters % 2)
     lim = 1e-13 if prec == P.OT_PREC_FP64 else 1e-6
     assert np.abs(X - Xo).max() <= lim * np.abs(Xo).max()
     assert np.abs(u - po).max() <= lim * np.abs(po).max() * 10
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP64, P.OT_PREC_FP32])
+def test_restarts_to_the_average_match_oracle(prec, engine):
+    """Fixed step with the adaptive restarts of Section 5 for 300 iterations: the same
+    restarts as the oracle, and the same final iterate.  Some restarts go to an average
+    that does not yet hold the current iterate (a fold pass runs first)."""
+    C, f, g = random_problem(11, 45, 77)
+    common = dict(tol=1e-12, max_iters=300, step_rule=1, restart_rule=0, output=1,
+                  eta0=0.6 / np.sqrt(122), omega0=0.8)
+    Xo, po, qo, ro, _ = oracle.solve(C, f, g, **common)
+    st, res, X, u, v = run_dense(C, f, g, prec, engine=engine, **common)
+    assert st == P.OT_NOT_CONVERGED and res["iterations"] == 300
+    if prec == P.OT_PREC_FP64:
+        assert res["restarts"] == ro["restarts"] > 0
+        assert np.abs(X - Xo).max() <= 1e-10 * np.abs(Xo).max()
+    assert res["mode_passes"][6] >= 1
 
 
 # ----------------------------------------------------------- full adaptive solves
