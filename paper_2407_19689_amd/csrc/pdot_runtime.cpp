@@ -515,7 +515,7 @@ public:
                     hipEvent_t *ev = &prof_ev_[2 * per_slot * (size_t)k];
                     for (size_t gi = 0; gi < ln.groups.size(); ++gi) {
                         const Group &g = ln.groups[gi];
-                        HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln) + g.first,
+                        HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln, k & 1) + g.first,
                                             d_counts() + l * kLaneCounts + gi, g.grid, ln.s, ev[2 * gi],
                                             ev[2 * gi + 1]));
                     }
@@ -755,7 +755,11 @@ private:
 
     Inst *d_insts() const { return (Inst *)(base_ + off_insts_); }
     int32_t *d_counts() const { return (int32_t *)(base_ + off_counts_); }
-    Tile *tiles(const Lane &ln) const { return (Tile *)(base_ + ln.off_tiles); }
+    // The tile table of a lane in forward (rev = 0) or reversed (rev = 1) order.
+    Tile *tiles(const Lane &ln, int rev = 0) const
+    {
+        return (Tile *)(base_ + ln.off_tiles) + (rev ? ln.tile_cap : 0);
+    }
     CombEntry *combs(const Lane &ln) const { return (CombEntry *)(base_ + ln.off_combs); }
     int32_t *d_rlist() const { return (int32_t *)(base_ + off_rlist_); }
 
@@ -946,6 +950,7 @@ private:
         }
 
         for (int g = 0; g < kNumCounts; ++g) h_counts_[g] = 0;
+        std::deque<std::vector<Tile>> rev_tiles;   // reversed tables, alive until the sync below
         bool recapture[kLanes];
         for (int l = 0; l < kLanes; ++l) {
             Lane &ln = lanes_[l];
@@ -976,10 +981,11 @@ private:
                     total += cap;
                 }
                 const int64_t ccap = std::max<int64_t>(256, (int64_t)cmb[l].size() * 3 / 2 + 64);
+                // two copies of the table: tile order forward, then reversed (see capture())
                 if (total > ln.tile_cap) {
-                    if (ln.tile_cap) arena_.release(ln.off_tiles, sizeof(Tile) * (size_t)ln.tile_cap);
+                    if (ln.tile_cap) arena_.release(ln.off_tiles, sizeof(Tile) * 2 * (size_t)ln.tile_cap);
                     ln.tile_cap = 0;
-                    if (!arena_.alloc(sizeof(Tile) * (size_t)total, &ln.off_tiles))
+                    if (!arena_.alloc(sizeof(Tile) * 2 * (size_t)total, &ln.off_tiles))
                         return fail(OT_ERR_OOM, "arena too small for the tile table");
                     ln.tile_cap = total;
                 }
@@ -996,9 +1002,15 @@ private:
             }
             for (size_t k = 0; k < keys[l].size(); ++k) {
                 const Group &g = ln.groups[map[k]];
-                if (!per[l][k].empty())
+                if (!per[l][k].empty()) {
                     HIP_TRY(hipMemcpyAsync(tiles(ln) + g.first, per[l][k].data(), sizeof(Tile) * per[l][k].size(),
                                            hipMemcpyHostToDevice, s_));
+                    // a copy of its own: the source of an asynchronous copy must stay unchanged
+                    // until the synchronisation below
+                    rev_tiles.emplace_back(per[l][k].rbegin(), per[l][k].rend());
+                    HIP_TRY(hipMemcpyAsync(tiles(ln, 1) + g.first, rev_tiles.back().data(),
+                                           sizeof(Tile) * rev_tiles.back().size(), hipMemcpyHostToDevice, s_));
+                }
                 h_counts_[l * kLaneCounts + map[k]] = (int32_t)per[l][k].size();
             }
             if (!cmb[l].empty())
@@ -1030,7 +1042,10 @@ private:
         for (int sl = 0; sl < ln.slots && e == hipSuccess; ++sl) {
             for (size_t gi = 0; gi < ln.groups.size() && e == hipSuccess; ++gi) {
                 const Group &g = ln.groups[gi];
-                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln) + g.first,
+                // consecutive slots stream the tiles in opposite orders: a pass starts on
+                // what the previous one touched last, which the Infinity Cache still holds
+                // when the plans outgrow it
+                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln, sl & 1) + g.first,
                                 d_counts() + l * kLaneCounts + gi, g.grid, ln.s);
             }
             if (e == hipSuccess)
@@ -1103,13 +1118,13 @@ ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, P
     }
     size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(int32_t) * kNumCounts);
     for (auto &l : P.L) total += align_up(l.bytes);
-    // each lane's tile and combine tables, sized as sync_tables sizes them
+    // each lane's tile (two copies) and combine tables, sized as sync_tables sizes them
     int64_t tcap[kLanes] = {};
     for (auto &kv : per) tcap[std::get<0>(kv.first)] += std::max<int64_t>(256, kv.second * 3 / 2 + 64);
     for (int l = 0; l < kLanes; ++l) {
         if (!used[l]) continue;
         const int64_t ccap = std::max<int64_t>(256, combs[l] * 3 / 2 + 64);
-        total += align_up(sizeof(Tile) * (size_t)tcap[l]) + align_up(sizeof(CombEntry) * (size_t)ccap);
+        total += align_up(sizeof(Tile) * 2 * (size_t)tcap[l]) + align_up(sizeof(CombEntry) * (size_t)ccap);
     }
     // resident lists, sized as sync_tables sizes them at most
     total += align_up(sizeof(int32_t) * (size_t)(((int64_t)count + 64 * kMaxGroups) * 3 / 2 + 64));
