@@ -276,18 +276,32 @@ def serving_leg(P, count=48, load=0.7, iter_cap=200000):
         torch.cuda.synchronize()
         with P.Server(budget, max_active=64, prm=prm) as srv:
             outs, t0 = {}, time.perf_counter()
-            for (inst, at), pr in zip(reqs, prs):
+            t_log = [t0]
+
+            def progress(n_sub):
+                # a line every 30 s with the submitted and completed counts
+                now = time.perf_counter()
+                if now - t_log[0] > 30.0:
+                    log(f"serving: {n_sub} of {len(reqs)} requests submitted, {len(outs)} done")
+                    t_log[0] = now
+
+            for k, ((inst, at), pr) in enumerate(zip(reqs, prs)):
                 while time.perf_counter() - t0 < at:
                     for d in srv.poll():
                         outs[d["ticket"]] = d
+                    progress(k)
                     time.sleep(0.0005)
                 st, tk = srv.submit(pr)
                 if st != P.OT_OK:
                     raise RuntimeError(f"submit failed: {P.STATUS_NAMES.get(st)} {P.ot_last_error()}")
-            if srv.drain(900.0) != P.OT_OK:
-                raise RuntimeError("server did not drain")
-            for d in srv.poll(4096):
-                outs[d["ticket"]] = d
+            t_end = time.perf_counter() + 900.0
+            while len(outs) < len(reqs):
+                for d in srv.poll(4096):
+                    outs[d["ticket"]] = d
+                if time.perf_counter() > t_end:
+                    raise RuntimeError("server did not drain")
+                progress(len(reqs))
+                time.sleep(0.002)
             return list(outs.values()), srv.stats()
 
     done, _ = run([(inst, 0.0) for _, inst in stream])
