@@ -522,6 +522,24 @@ def main():
                            "objective": rf["objective"], "rel_kkt": rf["rel_kkt"]}
             log(f"form {name}: {dtf:.3f} s, {rf['iterations']} iterations")
 
+    # the two smaller single-instance workloads (parity cases of the tests): 64 points in
+    # the unit square (squared Euclidean, one work-group runs it) and two 32x32 images;
+    # best of three solves to 1e-6 after one untimed solve
+    small = {}
+    if not args.no_forms:
+        for cfg in (1, 2):
+            ci = gen.config_instance(cfg, 0)
+            for pname, prec in (("fp32", FP32), ("fp64", FP64)):
+                gpu_solve(P, ci, args.tol, prec, 0)
+                runs = [gpu_solve(P, ci, args.tol, prec, 0) for _ in range(3)]
+                dts = min(r[0] for r in runs)
+                rr = runs[0][1]
+                small[f"config{cfg}_m{ci.m}_n{ci.n}_{pname}"] = {
+                    "seconds": round(dts, 5), "iterations": rr["iterations"],
+                    "iter_per_s": round(rr["iterations"] / dts, 1), "objective": rr["objective"],
+                    "rel_kkt": rr["rel_kkt"]}
+                log(f"config {cfg} ({ci.m}x{ci.n}) {pname}: {dts * 1e3:.2f} ms, {rr['iterations']} iterations")
+
     suite = None if args.no_suite else suite_leg(P, sizes=tuple(int(x) for x in args.suite_sizes.split(",")))
     batch = None if args.no_batch else batch_leg(P)
     serving = None if args.no_serving else serving_leg(P, count=args.serve_requests)
@@ -556,6 +574,7 @@ def main():
         "certified_bracket": bracket,
         "roofline": roof,
         "forms": forms,
+        "small_configs": small,
         "suite": suite,
         "batch": batch,
         "serving": serving,
