@@ -960,6 +960,42 @@ __device__ __forceinline__ IndexIn index_load(const PDOT_CONST Inst &I, const Ct
     return in;
 }
 
+// The same inputs for every mode and both versions of the double-buffered vectors, loaded
+// before the control block has arrived (which version is current is known only then).
+struct IndexPre {
+    double fi, pc[2], pb[2], rc[2], sb0, an0;
+};
+
+__device__ __forceinline__ IndexPre index_prefetch(const PDOT_CONST Inst &I, bool rows, int64_t idx)
+{
+    IndexPre x;
+    x.fi = rows ? gp(I.f)[idx] : gp(I.g)[idx];
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        x.pc[v] = gp(rows ? I.p[v] : I.q[v])[idx];
+        x.pb[v] = gp(rows ? I.pb[v] : I.qb[v])[idx];
+        x.rc[v] = gp(rows ? I.rs[v] : I.cs[v])[idx];
+    }
+    x.sb0 = gp(rows ? I.rsb : I.csb)[idx];
+    x.an0 = gp(rows ? I.pa : I.qa)[idx];
+    return x;
+}
+
+// The inputs index_load would have loaded for this mode and these versions.
+__device__ __forceinline__ IndexIn index_select(const IndexPre &x, const Ctl &st, int mode)
+{
+    IndexIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    in.fi = x.fi;
+    if (mode == M_INIT || mode == M_FOLD) return in;
+    // selects, not a run-time index (which could put the arrays in scratch memory)
+    in.pc0 = st.pv ? x.pc[1] : x.pc[0];
+    in.pb0 = st.pbv ? x.pb[1] : x.pb[0];
+    in.rc0 = st.rsv ? x.rc[1] : x.rc[0];
+    if (mode == M_FULL || mode == M_RESTART) in.sb0 = x.sb0;
+    if (mode == M_RESTART) in.an0 = x.an0;
+    return in;
+}
+
 // Work on one row (rows) or one column once its sums of the pass are complete (sv; 0 for
 // modes that need none): KKT pieces of the current iterate and of the average, the dual
 // step of the trial (Algorithm 2, with the extrapolated sums) and its running average,
@@ -1044,23 +1080,22 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         if (e + (int)gridDim.x < nents) next = cp(ents)[e + gridDim.x];
         const PDOT_CONST Inst &I = cp(insts)[E.inst];
         const Ctl st = *gp(I.ctl);
-        const int mode = st.mode;
-        if (mode == M_IDLE) continue;
 
         const bool rows = E.kind == 0;
         const int64_t len = rows ? I.m : I.n;
         const int64_t idx = (int64_t)E.start + lane;
         const bool valid = idx < len;
-        const bool sums = mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY;
 
-        // wave 0 loads its per-entry vectors first; they do not depend on the partials
-        IndexIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        if (wave == 0 && valid) in = index_load(I, st, mode, rows, idx);
+        // The per-entry vectors (wave 0) and the per-tile partial sums of this slice are
+        // loaded before the control block has arrived, so that the three sets of loads are
+        // in flight together; modes that use no sums (and idle instances) discard them.
+        IndexPre pre{};
+        if (wave == 0 && valid) pre = index_prefetch(I, rows, idx);
 
         // phase 1: the per-tile partial sums of this slice, in a fixed order (wave w adds
         // partials w, w+4, w+8, ... with up to 16 loads in flight)
         double sv = 0.0;
-        if (sums) {
+        {
             const int np = rows ? I.ncb : I.nrb;
             const PDOT_GLOBAL double *src = gp(rows ? (const double *)I.rowpart : (const double *)I.colpart);
             if (valid) {
@@ -1076,8 +1111,13 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                         if (base + 4 * k < np) sv += v[k];
                 }
             }
-            part[wave][lane] = sv;
         }
+        const int mode = st.mode;
+        if (mode == M_IDLE) continue;
+        const bool sums = mode == M_TRIAL || mode == M_FULL || mode == M_VERIFY;
+        if (sums) part[wave][lane] = sv;
+        IndexIn in{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (wave == 0 && valid) in = index_select(pre, st, mode);
 
         // the tile scalars of this entry's share of the pass's tiles (wave 1)
         if (wave == 1) {
