@@ -15,6 +15,8 @@
 //   sums       X+ 1, (X+ - X) 1, X+^T 1, (X+ - X)^T 1            (matrix-free A, Section 3.1)
 //   step norm  ||X+ - X||_F^2                                     (step-size rule, Section 5)
 //   average    Xbar <- (1-a) Xbar + a X                           (Algorithm 2, last update)
+//              every other pass, for the start iterate and then for the trial (two folds
+//              in registers, one store)
 //   KKT parts  ||[p_i+q_j-C_ij]^+||^2 for (p,q) and (pbar,qbar), <C,X>, <C,Xbar>
 // Row sums are wave reductions; column sums stay in registers over the tile's rows, are
 // combined across the four waves in LDS and written as one partial row per tile; k_combine
