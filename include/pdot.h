@@ -140,8 +140,13 @@ typedef struct {
     double beta_sufficient, beta_necessary, beta_artificial, beta_basic;
     double theta, omega0, eta0, eps_zero;
     double step_reduction_exp, step_growth_exp;
-    int32_t tile_vec;         /* columns per lane (1, 2, 4), 0 = autotuned    */
-    int32_t tile_rows;        /* rows per tile (multiple of 16), 0 = autotuned */
+    int32_t tile_vec;         /* columns per lane (1, 2, 4); 0: the library's choice
+                                 (the widest lane that still gives about 1024 tiles
+                                 of 16 rows)                                     */
+    int32_t tile_rows;        /* rows per tile (multiple of 16); 0: the library's
+                                 choice (about four tiles per compute unit).  The
+                                 Python helper tiles_for() returns the shapes that
+                                 the autotuner measured best on gfx950           */
     int32_t profile;          /* 1: launch blocks of 16 slots back to back without a
                                  graph, every launch stamping its own HIP events
                                  (ot_result.pass_ms, combine_ms)                     */

@@ -128,10 +128,14 @@ bool finite_nonneg(const std::vector<double> &v)
     return true;
 }
 
-int default_vec(int64_t n)
+// The widest lane (more bytes per load) whose tiles of 16 rows still number about four per
+// compute unit (1024); narrower lanes fill the GPU on mid-size instances (the autotuner
+// picks 1 column per lane for 1024 x 1024 grids and 4 for 4096 x 4096).
+int default_vec(int64_t m, int64_t n)
 {
-    if (n >= 256) return 4;
-    if (n >= 128) return 2;
+    const int64_t rb = (m + 15) / 16;
+    for (int v = 4; v >= 2; v /= 2)
+        if (n >= 64 * v && rb * ((n + 64 * v - 1) / (64 * v)) >= 1024) return v;
     return 1;
 }
 
@@ -194,7 +198,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     const int64_t elems = pb.m * pb.n;
     L.resident = (prm.engine == 0 && elems <= OT_RESIDENT_MAX_ELEMS) ||
                  (prm.engine == 2 && elems <= OT_RESIDENT_HARD_MAX_ELEMS);
-    L.vec = pb.tile_vec > 0 ? pb.tile_vec : (prm.tile_vec ? prm.tile_vec : default_vec(pb.n));
+    L.vec = pb.tile_vec > 0 ? pb.tile_vec : (prm.tile_vec ? prm.tile_vec : default_vec(pb.m, pb.n));
     if (L.vec != 1 && L.vec != 2 && L.vec != 4) return fail(OT_ERR_INVALID, "tile_vec must be 1, 2 or 4");
     // the resident kernel has no 4-column variant (it would spill registers)
     if (L.resident && L.vec == 4) L.vec = 2;
