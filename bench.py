@@ -189,12 +189,13 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def problems_autotuned(P, insts, precision, kind=None):
-    """Device problems with the autotuned tile shape of each instance (plan output off)."""
+def problems_autotuned(P, insts, precision, kind=None, shared=False):
+    """Device problems with the autotuned tile shape of each instance (plan output off);
+    shared: the shapes for instances solved together (autotune.tiles_for)."""
     from paper_2407_19689_amd import autotune
     out = []
     for inst in insts:
-        v, r = autotune.tiles_for(inst.m, inst.n, precision, kind or inst.kind)
+        v, r = autotune.tiles_for(inst.m, inst.n, precision, kind or inst.kind, shared=shared)
         pr, _ = P.problem_from_instance(inst, precision=precision, tol=inst.tol, want_plan=False,
                                         tile_vec=v, tile_rows=r)
         out.append(pr)
@@ -210,7 +211,7 @@ def batch_leg(P, count=256, seq_every=4):
     FP32 = P.OT_PREC_FP32
     insts = gen.batch_instances(count)
     prm = P.params(tol=1e-4, precision=FP32, time_limit_s=300.0)
-    prs = problems_autotuned(P, insts, FP32)
+    prs = problems_autotuned(P, insts, FP32, shared=True)
     torch.cuda.synchronize()
     t = time.perf_counter()
     st, res = P.ot_solve_batch(prs, prm)
@@ -244,7 +245,7 @@ def batch_leg(P, count=256, seq_every=4):
     return {
         "workload": f"{count} instances, m,n log-uniform in [32,2048] (master seed 300), 3-GMM "
                     "points in R^3, Euclidean cost regenerated in-kernel, lognormal marginals, "
-                    "FP32 plan, rel-KKT tol 1e-4, autotuned tiles",
+                    "FP32 plan, rel-KKT tol 1e-4, autotuned tile rows with the widest lanes",
         "makespan_s": round(makespan, 4), "solves_per_s": round(count / makespan, 2),
         "completion_p50_s": round(percentile(done, 50), 4),
         "completion_p99_s": round(percentile(done, 99), 4),

@@ -47,8 +47,21 @@ def load_cache():
     return _cache
 
 
-def tiles_for(m, n, precision, kind):
-    """(vec, rows) from the cache for the nearest tuned bucket, else (0, 0)."""
+def tiles_for(m, n, precision, kind, shared=False):
+    """(vec, rows) from the cache for the nearest tuned bucket, else (0, 0).
+
+    The cache holds the shapes measured best for an instance running alone, where narrow
+    lanes (1-2 columns) buy more tiles to fill the GPU.  With shared=True (many instances
+    solved together, which fill the GPU between them) the lane is the widest the instance's
+    n allows (fewer per-row instructions per byte) and the rows stay the tuned ones: on the
+    256-instance batch that was 5 % shorter makespan and 8 % lower completion p50."""
+    v, r = _tuned(m, n, precision, kind)
+    if shared:
+        v = 4 if n >= 256 else (2 if n >= 128 else 1)
+    return v, r
+
+
+def _tuned(m, n, precision, kind):
     cache = load_cache()
     bm, bn = bucket(m, n)
     best, dist = (0, 0), None

@@ -19,6 +19,11 @@ def test_tiles_for_picks_the_nearest_tuned_bucket(tmp_path, monkeypatch):
     assert autotune.tiles_for(2000, 1500, 0, "points_euclid") == (2, 32)
     # nothing tuned for this kind: (0, 0) selects the library's built-in shape
     assert autotune.tiles_for(2000, 1500, 1, "grid_sqeuclid") == (0, 0)
+    # instances solved together: the widest lane n allows, the tuned rows
+    assert autotune.tiles_for(2000, 1500, 0, "points_euclid", shared=True) == (4, 32)
+    assert autotune.tiles_for(2000, 200, 0, "points_euclid", shared=True) == (2, 32)
+    assert autotune.tiles_for(40, 30, 1, "points_euclid", shared=True) == (1, 16)
+    assert autotune.tiles_for(2000, 1500, 1, "grid_sqeuclid", shared=True) == (4, 0)
 
 
 def test_tiles_for_without_a_cache(tmp_path, monkeypatch):
