@@ -7,14 +7,17 @@ to relative KKT 1e-6.  One timed step is one complete solve (every iteration of 
 the whole hot path: primal step, sums, dual step, averaging, KKT, restart and step-size
 checks).  `value` is accepted PDHG iterations per second over the timed solves.
 
-Also reported: time to 1e-4 and 1e-6, the stored-FP32-cost and plain-FP64 forms, the
-streaming kernel against the HBM roofline (durations from HIP events around every pass
-launch of one profiled solve), a batch of 256 uneven instances in one ot_solve_batch
-(makespan, completion p50/p99, against solving a subset one by one), a continuous-
-batching server fed a Poisson request stream (latency p50/p99, solves/s), and the FP64
-CPU oracle timed on a bounded sample.
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-batch] [--no-serving]
-       [--serve-requests 2000]
+Also reported: time to 1e-4 and 1e-6 (also averaged over five images), the
+stored-FP32-cost and plain-FP64 forms, the smaller workloads (64 points, 1024 x 1024
+grid) in both precisions, the rounded plan's certified bracket, the streaming kernel
+against the HBM roofline (durations from the events stamped by every pass launch of one
+profiled solve, launched in back-to-back blocks of 16 slots), a synthetic suite with the
+paper's reporting, a batch of 256 uneven instances in one ot_solve_batch (makespan,
+completion p50/p99, against solving a subset one by one), a continuous-batching server
+fed a Poisson request stream (latency p50/p99, solves/s), and the FP64 CPU oracle timed
+on a bounded sample.
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+       [--no-suite] [--no-batch] [--no-serving] [--serve-requests N]
 """
 import argparse
 import json
