@@ -273,6 +273,7 @@ int orc_solve(int64_t m, int64_t n, const double *C, const double *f, const doub
               int32_t nthreads)
 {
 #ifdef _OPENMP
+    const int threads_before = omp_get_max_threads();
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
     (void)nthreads;
@@ -520,6 +521,9 @@ int orc_solve(int64_t m, int64_t n, const double *C, const double *f, const doub
     free(p); free(q); free(pn); free(qn); free(pb); free(qb); free(pa); free(qa);
     free(er); free(ec); free(dr); free(dc);
     problem_free(&P);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(threads_before);   /* the caller's setting again */
+#endif
     return (int)ntrace;
 }
 
