@@ -47,7 +47,9 @@ typedef enum {
     OT_ERR_INVALID = 1,    /* bad sizes, pointers, non-finite data, sum f != sum g, tol <= 0 */
     OT_ERR_OOM = 2,        /* device allocation failed or workspace too small             */
     OT_ERR_DEVICE = 3,     /* a HIP runtime call failed                                    */
-    OT_NOT_CONVERGED = 4,  /* iteration, pass or time limit reached; outputs are filled    */
+    OT_NOT_CONVERGED = 4,  /* iteration, pass or time limit reached, or the returned arrays
+                              failed the final verification verify_retries + 1 times;
+                              outputs are filled                                        */
     OT_ERR_NUMERIC = 5,    /* a KKT or step-size scalar became NaN/Inf                     */
     OT_ERR_BUSY = 6        /* server queue full or request over its memory budget          */
 } ot_status;
@@ -93,6 +95,23 @@ typedef struct {
     double scale;       /* grid kind: multiplier of the squared distance */
 } ot_cost;
 
+/* One record of the solver's control sequence (Section 5): a rejected step trial, or an
+ * accepted iteration with the relative KKT errors of the current iterate and of the
+ * average, the restart candidate and the restart decision.  The same fields as the FP64
+ * oracle's trace, so the two can be compared decision by decision. */
+typedef struct {
+    int64_t pass;        /* step trials evaluated so far, this one included              */
+    int64_t iter;        /* accepted iterations so far (this one included if accepted)   */
+    int32_t accepted;    /* 1: the trial met the step-size bound                         */
+    int32_t restart;     /* 0 none; 1, 2, 3: restart conditions (i), (ii), (iii) fired   */
+    int32_t cand_avg;    /* restart candidate is the average                             */
+    int32_t pad;
+    double eta_used;     /* step size of the trial                                       */
+    double eta_bar;      /* its step-size bound (+inf for a constant step)               */
+    double k_cur, k_avg; /* relative KKT of the current iterate and of the average       */
+    double omega;        /* primal weight in use                                         */
+} ot_trace_rec;
+
 /* One OT instance with its outputs. */
 typedef struct {
     ot_cost cost;
@@ -105,6 +124,10 @@ typedef struct {
     double *v_out;       /* nullable; n, the column duals q                          */
     int32_t tile_vec;    /* > 0 overrides ot_params.tile_vec for this instance       */
     int32_t tile_rows;   /* > 0 overrides ot_params.tile_rows for this instance      */
+    ot_trace_rec *trace; /* nullable; host or device, trace_cap records: the first
+                            trace_cap control records of the solve (ot_result.trace_len
+                            gives how many were written)                             */
+    int64_t trace_cap;
 } ot_problem;
 
 /* Solver parameters.  Defaults (ot_params_default) are the paper's constants:
@@ -159,6 +182,12 @@ typedef struct {
                                  the resident path only pays below a few thousand entries.
                                  The choice depends on the instance only, so an instance
                                  takes the same path solo, in a batch or in the server.  */
+    int32_t verify_retries;   /* final verifications that may fail (the returned arrays
+                                 above tol although the running estimate met it) before
+                                 the solve returns OT_NOT_CONVERGED; after a failure the
+                                 internal threshold is tightened and iteration continues.
+                                 Default 8.                                           */
+    int32_t pad0;
 } ot_params;
 
 #define OT_RESIDENT_MAX_ELEMS 4096
@@ -194,6 +223,7 @@ typedef struct {
     int64_t avg_fold_passes;   /* kinds 2 and 3 that also folded their start iterate and
                                   their trial into the stored running average (the average
                                   is read and written every other pass)                  */
+    int64_t trace_len;         /* control records written to ot_problem.trace           */
 } ot_result;
 
 /* Fill *prm with the defaults described above (precision OT_PREC_FP32). */

@@ -18,7 +18,7 @@ from ._abi import (  # noqa: F401
     OT_OK, OT_ERR_INVALID, OT_ERR_OOM, OT_ERR_DEVICE, OT_NOT_CONVERGED, OT_ERR_NUMERIC,
     OT_ERR_BUSY, OT_PREC_FP64, OT_PREC_FP32, OT_COST_DENSE, OT_COST_POINTS_SQEUCLID,
     OT_COST_POINTS_EUCLID, OT_COST_GRID_SQEUCLID, OT_COST_GRID_L1, OT_COST_GRID_L2,
-    OT_COST_GRID_LINF, OtCost, OtParams, OtProblem, OtResult,
+    OT_COST_GRID_LINF, OtCost, OtParams, OtProblem, OtResult, OtTraceRec,
     OtServerCfg, OtCompletion, OtServerStats, OtBracket, STATUS_NAMES,
 )
 
@@ -70,15 +70,25 @@ def params(**kw) -> OtParams:
 class Problem:
     """An OtProblem plus references to the buffers it points into."""
 
-    def __init__(self, raw: OtProblem, keep):
+    def __init__(self, raw: OtProblem, keep, trace_buf=None):
         self.raw = raw
         self.keep = keep
+        self.trace_buf = trace_buf
+
+    def trace(self, count):
+        """The first `count` control records (ot_result.trace_len) as dicts."""
+        out = []
+        for i in range(min(count, len(self.trace_buf) if self.trace_buf is not None else 0)):
+            r = self.trace_buf[i]
+            out.append({k.rstrip("_"): getattr(r, k) for k, _ in OtTraceRec._fields_})
+        return out
 
 
 def problem(kind, m, n, f, g, C=None, ldc=None, x=None, y=None, side=0, scale=1.0,
             store=0, tol=0.0, X_out=None, u_out=None, v_out=None, tile_vec=0,
-            tile_rows=0) -> Problem:
-    """Build an ot_problem from torch tensors or numpy arrays (host or device)."""
+            tile_rows=0, trace_cap=0) -> Problem:
+    """Build an ot_problem from torch tensors or numpy arrays (host or device).
+    trace_cap > 0 gives the problem a host buffer for that many control records."""
     for a, nm in ((f, "f"), (g, "g"), (C, "C"), (x, "x"), (y, "y"), (u_out, "u_out"),
                   (v_out, "v_out")):
         _check_f64(a, nm)
@@ -106,7 +116,12 @@ def problem(kind, m, n, f, g, C=None, ldc=None, x=None, y=None, side=0, scale=1.
     pr.v_out = _ptr(v_out)
     pr.tile_vec = tile_vec
     pr.tile_rows = tile_rows
-    return Problem(pr, [f, g, C, x, y, X_out, u_out, v_out])
+    tbuf = None
+    if trace_cap > 0:
+        tbuf = (OtTraceRec * trace_cap)()
+        pr.trace = ct.addressof(tbuf)
+        pr.trace_cap = trace_cap
+    return Problem(pr, [f, g, C, x, y, X_out, u_out, v_out], tbuf)
 
 
 def ot_workspace_size(prob: Problem, prm: OtParams) -> int:
@@ -254,7 +269,7 @@ _KINDS = {
 
 
 def problem_from_instance(inst, device="cuda", precision=OT_PREC_FP32, store=0, dense=False,
-                          tol=0.0, want_plan=True, tile_vec=0, tile_rows=0):
+                          tol=0.0, want_plan=True, tile_vec=0, tile_rows=0, trace_cap=0):
     """Place an instance (attributes m, n, f, g, kind, x, y, side, scale, dense_cost())
     in device memory with torch and allocate the outputs.  Returns (Problem, outputs)."""
     import torch
@@ -269,26 +284,31 @@ def problem_from_instance(inst, device="cuda", precision=OT_PREC_FP32, store=0, 
     if dense or inst.kind not in _KINDS:
         C = torch.as_tensor(np.ascontiguousarray(inst.dense_cost(), dtype=np.float64), device=dev)
         pr = problem(OT_COST_DENSE, inst.m, inst.n, f, g, C=C, tol=tol, X_out=X, u_out=u, v_out=v,
-                     tile_vec=tile_vec, tile_rows=tile_rows)
+                     tile_vec=tile_vec, tile_rows=tile_rows, trace_cap=trace_cap)
         return pr, out
     kind = _KINDS[inst.kind]
     if kind in (OT_COST_GRID_SQEUCLID, OT_COST_GRID_L1, OT_COST_GRID_L2, OT_COST_GRID_LINF):
         pr = problem(kind, inst.m, inst.n, f, g, side=inst.side, scale=inst.scale, store=store,
-                     tol=tol, X_out=X, u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows)
+                     tol=tol, X_out=X, u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows,
+                     trace_cap=trace_cap)
     else:
         x = torch.as_tensor(np.ascontiguousarray(inst.x, dtype=np.float64), device=dev)
         y = torch.as_tensor(np.ascontiguousarray(inst.y, dtype=np.float64), device=dev)
         pr = problem(kind, inst.m, inst.n, f, g, x=x, y=y, store=store, tol=tol, X_out=X,
-                     u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows)
+                     u_out=u, v_out=v, tile_vec=tile_vec, tile_rows=tile_rows,
+                     trace_cap=trace_cap)
     return pr, out
 
 
 def solve_instance(inst, prm: OtParams = None, device="cuda", store=0, dense=False, tol=0.0,
-                   stream=None, **kw):
-    """ot_solve on one instance; returns (status, result dict, outputs dict of tensors)."""
+                   stream=None, trace_cap=0, **kw):
+    """ot_solve on one instance; returns (status, result dict, outputs dict of tensors).
+    With trace_cap > 0 the outputs also hold the control records under "trace"."""
     if prm is None:
         prm = params(**kw)
     pr, out = problem_from_instance(inst, device=device, precision=prm.precision, store=store,
-                                    dense=dense, tol=tol)
+                                    dense=dense, tol=tol, trace_cap=trace_cap)
     st, res = ot_solve(pr, prm, stream=stream)
+    if trace_cap > 0:
+        out["trace"] = pr.trace(res.trace_len)
     return st, res.as_dict(), out

@@ -51,6 +51,22 @@ class OtCost(ct.Structure):
     ]
 
 
+class OtTraceRec(ct.Structure):
+    _fields_ = [
+        ("pass_", ct.c_int64),
+        ("iter", ct.c_int64),
+        ("accepted", ct.c_int32),
+        ("restart", ct.c_int32),
+        ("cand_avg", ct.c_int32),
+        ("pad", ct.c_int32),
+        ("eta_used", ct.c_double),
+        ("eta_bar", ct.c_double),
+        ("k_cur", ct.c_double),
+        ("k_avg", ct.c_double),
+        ("omega", ct.c_double),
+    ]
+
+
 class OtProblem(ct.Structure):
     _fields_ = [
         ("cost", OtCost),
@@ -64,6 +80,8 @@ class OtProblem(ct.Structure):
         ("v_out", ct.c_void_p),
         ("tile_vec", ct.c_int32),
         ("tile_rows", ct.c_int32),
+        ("trace", ct.c_void_p),
+        ("trace_cap", ct.c_int64),
     ]
 
 
@@ -95,6 +113,8 @@ class OtParams(ct.Structure):
         ("tile_rows", ct.c_int32),
         ("profile", ct.c_int32),
         ("engine", ct.c_int32),
+        ("verify_retries", ct.c_int32),
+        ("pad0", ct.c_int32),
     ]
 
 
@@ -124,6 +144,7 @@ class OtResult(ct.Structure):
         ("estimate_parts", ct.c_double * 3),
         ("estimate_objective", ct.c_double),
         ("avg_fold_passes", ct.c_int64),
+        ("trace_len", ct.c_int64),
     ]
 
     def as_dict(self):

@@ -60,7 +60,7 @@ struct Prm {
     double tol;
     int64_t max_iters, max_passes;
     int32_t kkt_mode, step_rule, restart_rule, avg_weighting;
-    int32_t pwu, output, pad0, pad1;
+    int32_t pwu, output, verify_retries, pad1;
     double beta_suff, beta_nec, beta_art, beta_basic;
     double theta, eps_zero, red_exp, grow_exp;
 };
@@ -88,6 +88,17 @@ struct Ctl {
     double e_rel[3], e_obj;  // running estimate of the candidate (rel_P, rel_D, rel_G, <C,X>)
     double pobjb;           // <C, Xbar> of the stored average when it holds the current
                             // iterate (computed by the pass that wrote it, before rounding)
+    int64_t ntrace;         // control records written to the instance's trace buffer
+    int64_t tr_pass;        // accepted trial awaiting its record: its pass number, the
+    double tr_eta, tr_eta_bar;   // step it used and the step bound it met
+};
+
+// One control record (the layout of ot_trace_rec in the public header): a rejected trial,
+// or an accepted iteration with its KKT values, candidate and restart decision.
+struct TraceRec {
+    int64_t pass, iter;
+    int32_t accepted, restart, cand_avg, pad;
+    double eta_used, eta_bar, k_cur, k_avg, omega;
 };
 
 struct Inst {
@@ -111,6 +122,8 @@ struct Inst {
     double *combscal;       // [ncomb][kNB]
     uint32_t *counter;
     Ctl *ctl;
+    TraceRec *trace;        // nullable: control records of the solve
+    int64_t trace_cap;
     Prm prm;
 };
 

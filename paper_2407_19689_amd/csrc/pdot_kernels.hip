@@ -152,10 +152,21 @@ __device__ __forceinline__ double sqdist(P1 xi, P2 yj, int dim)
 
 // Costs are evaluated in the working precision TX and widened to FP64; the materialising
 // kernel calls the same functions, so stored and regenerated costs are bit-identical.
-template <typename TX>
-__device__ __forceinline__ double round_to(double v)
+// Points kinds: the squared distance of the FP64 coordinates in FP64 (exact differences,
+// each product and sum rounded once); an FP32 plan then rounds it to FP32 once, and the
+// Euclidean kind takes the square root of that FP32 value in FP32, so the FP32 form pays
+// no FP64 square root per entry (the cost stays within an FP32 ulp or two of the FP64
+// distance, the rounding the FP32 cost stream has anyway).
+template <typename TX, int COST, typename P1, typename P2>
+__device__ __forceinline__ double point_cost(P1 xi, P2 yj, int dim)
 {
-    return (double)(TX)v;
+    const double s2 = sqdist(xi, yj, dim);
+    if constexpr (sizeof(TX) == 8) {
+        return COST == C_PTS_EU ? sqrt(s2) : s2;
+    } else {
+        const float s = (float)s2;
+        return (double)(COST == C_PTS_EU ? sqrtf(s) : s);
+    }
 }
 
 // Grid kinds, C_ij = scale * d(pixel_i, pixel_j) for pixels (a, b), with d the squared
@@ -486,9 +497,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
                     } else if constexpr (kGrid) {
                         cd = grid_cost<TX, COST>(R.gia[u], R.gib[u], gja[v], gjb[v], scale, scale32);
                     } else {
-                        double s2 = sqdist(R.xi[u], yc[v], dim);
-                        if constexpr (COST == C_PTS_EU) s2 = sqrt(s2);
-                        cd = round_to<TX>(s2);
+                        cd = point_cost<TX, COST>(R.xi[u], yc[v], dim);
                     }
                 }
                 xn_out[v] = (TX)0;
@@ -691,7 +700,7 @@ __device__ __forceinline__ double rel_kkt(const Prm &P, double nb, double nc, do
     return sqrt(rp * rp + rd * rd + rg * rg);
 }
 
-enum { ST_RUNNING = -1, ST_OK = 0, ST_NOT_CONVERGED = 4, ST_NUMERIC = 5 };
+enum { ST_RUNNING = -1, ST_OK = 0, ST_DEVICE = 3, ST_NOT_CONVERGED = 4, ST_NUMERIC = 5 };
 
 __device__ __forceinline__ void finish(Ctl &c, const Prm &P, int status)
 {
@@ -718,20 +727,50 @@ __device__ __forceinline__ bool limits_hit(const Ctl &c, const Prm &P)
     return c.T >= P.max_iters || c.passes >= P.max_passes || c.stop;
 }
 
+// Where the control appends its records (null: no trace), and how many fit.
+struct TraceOut {
+    TraceRec *buf;
+    int64_t cap;
+};
+
+__device__ __forceinline__ void trace_put(Ctl &c, const TraceOut &to, int64_t pass, int32_t accepted,
+                                          int32_t restart, double eta_used, double eta_bar, double kc,
+                                          double ka)
+{
+    if (!to.buf || c.ntrace >= to.cap) return;
+    TraceRec r;
+    r.pass = pass;
+    r.iter = c.T;
+    r.accepted = accepted;
+    r.restart = restart;
+    r.cand_avg = accepted ? c.cand_avg : 0;
+    r.pad = 0;
+    r.eta_used = eta_used;
+    r.eta_bar = eta_bar;
+    r.k_cur = kc;
+    r.k_avg = ka;
+    r.omega = c.omega;
+    gp(to.buf)[c.ntrace] = r;
+    c.ntrace += 1;
+}
+
 // Step-size check of the trial (Section 5, adaptive step size).
 // g_red = (T+1)^-a and g_grow = (T+1)^-b are evaluated by the caller (in parallel with
 // its loads) for the current T.
 // aux: <C, next average> of a pass that folded two iterates.
+// A rejected trial is traced at once; an accepted one when its KKT values and restart
+// decision are known (the next M_FULL control), from the fields kept in tr_*.
 __device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, double dy2, double inter,
-                            double aux, double g_red, double g_grow)
+                            double aux, double g_red, double g_grow, const TraceOut &to)
 {
     c.passes += 1;
     const double eta_used = c.eta;
     bool accept = true;
+    double eta_bar = INFINITY;
     if (P.step_rule == 0) {
         const double num = c.omega * dx2 + dy2 / c.omega;
         const double den = 2.0 * fabs(inter);
-        const double eta_bar = den > 0.0 ? num / den : INFINITY;
+        eta_bar = den > 0.0 ? num / den : INFINITY;
         accept = c.eta <= eta_bar;
         const double shrink = (1.0 - g_red) * eta_bar;
         const double grow = (1.0 + g_grow) * c.eta;
@@ -769,15 +808,19 @@ __device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, do
         const double w = P.avg_weighting == 1 ? 1.0 : eta_used;
         c.wsum += w;
         c.a_fold = w / c.wsum;
+        c.tr_pass = c.passes;
+        c.tr_eta = eta_used;
+        c.tr_eta_bar = eta_bar;
         c.mode = M_FULL;
     } else {
+        trace_put(c, to, c.passes, 0, 0, eta_used, eta_bar, 0.0, 0.0);
         c.mode = M_TRIAL;
         if (c.passes >= P.max_passes || c.stop) finish(c, P, ST_NOT_CONVERGED);
     }
 }
 
 __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const double *ts,
-                        double g_red, double g_grow)
+                        double g_red, double g_grow, const TraceOut &to)
 {
     // constant indices only: an array of the control block indexed at run time would put
     // the whole block in scratch memory
@@ -811,7 +854,7 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
         return;
     }
     if (mode == M_TRIAL) {
-        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], ts[TS_AUX], g_red, g_grow);
+        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], ts[TS_AUX], g_red, g_grow, to);
         return;
     }
     if (mode == M_FULL) {
@@ -835,6 +878,7 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
         }
         c.K_cand = K;
         if (K <= c.tol_eff) {
+            trace_put(c, to, c.tr_pass, 1, 0, c.tr_eta, c.tr_eta_bar, kc, ka);
             finish(c, P, ST_OK);
             return;
         }
@@ -851,6 +895,7 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
                 c.K_cand = K;
             }
         }
+        trace_put(c, to, c.tr_pass, 1, restart, c.tr_eta, c.tr_eta_bar, kc, ka);
         if (restart) {
             c.K_start = K;
             c.K_prev = K;
@@ -868,7 +913,7 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
             finish(c, P, ST_NOT_CONVERGED);
             return;
         }
-        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], ts[TS_AUX], g_red, g_grow);
+        step_decide(c, P, ts[TS_DX2], cs[CS_DY2], cs[CS_INTER], ts[TS_AUX], g_red, g_grow, to);
         return;
     }
     if (mode == M_FOLD) {
@@ -924,16 +969,20 @@ __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const do
         c.r_kkt = K;
         if (c.status == ST_OK && !(K == K)) {
             c.status = ST_NUMERIC;
-        } else if (c.status == ST_OK && K > P.tol && c.verify_fails < 8) {
-            // The running estimate met the tolerance but the returned arrays do not (FP32
-            // storage of the average); tighten the internal threshold and keep iterating
-            // from the unchanged state.
-            c.verify_fails += 1;
-            const double ratio = P.tol / K;
-            c.tol_eff = c.tol_eff * (ratio < 0.9 ? ratio : 0.9);
-            c.status = ST_RUNNING;
-            c.mode = M_TRIAL;
-            return;
+        } else if (c.status == ST_OK && K > P.tol) {
+            if (c.verify_fails < P.verify_retries && !limits_hit(c, P)) {
+                // The running estimate met the tolerance but the returned arrays do not
+                // (FP32 storage of the average); tighten the internal threshold and keep
+                // iterating from the unchanged state.
+                c.verify_fails += 1;
+                const double ratio = P.tol / K;
+                c.tol_eff = c.tol_eff * (ratio < 0.9 ? ratio : 0.9);
+                c.status = ST_RUNNING;
+                c.mode = M_TRIAL;
+                return;
+            }
+            // the returned arrays (filled) fail the termination test: not converged
+            c.status = ST_NOT_CONVERGED;
         }
         c.mode = M_IDLE;
         return;
@@ -1054,6 +1103,36 @@ __device__ __forceinline__ void index_work(const PDOT_CONST Inst &I, const Ctl &
     }
 }
 
+// Record words of the combine hand-off.  A word holds the bits of its value plus one, so
+// zero (its state before the value is written, and again after the last work-group has
+// taken it) is never a value: a computed double never has the all-ones bit pattern (a NaN
+// payload the arithmetic does not produce).  Every word is written once and read once per
+// slot; the kernel boundary between slots orders a word's reset before its next value.
+__device__ __forceinline__ void rec_put(PDOT_GLOBAL uint64_t *w, double v)
+{
+    __hip_atomic_store(w, (uint64_t)__double_as_longlong(v) + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait for a word (its store was issued before the writer moved the counter, so it
+// arrives; the wait is bounded all the same: after kRecSpin loads `lost` is set and the
+// caller stops the instance with a device error instead of waiting on), take its value
+// and reset it.
+constexpr int kRecSpin = 1 << 20;
+__device__ __forceinline__ double rec_take(PDOT_GLOBAL uint64_t *w, bool &lost)
+{
+    uint64_t b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int k = 0; b == 0 && k < kRecSpin; ++k) {
+        __builtin_amdgcn_s_sleep(1);
+        b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (b == 0) {
+        lost = true;
+        return 0.0;
+    }
+    __hip_atomic_store(w, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)(b - 1u));
+}
+
 // The combine kernel: one work-group per slice of 64 rows or 64 columns of an instance.
 //  1. adds the per-tile partial sums of the slice (the four waves split the partials; all
 //     loads of a wave are in flight together; fixed order);
@@ -1069,7 +1148,8 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
     __shared__ double part[4][64];
     __shared__ double tsum[kNS];
     __shared__ double fin[4][kNB];
-    __shared__ int is_last;
+    __shared__ int is_last, lost_any;
+    if (threadIdx.x == 0) lost_any = 0;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     // The launch grid never exceeds the entry table's capacity: the first entry is read
@@ -1149,21 +1229,23 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 #pragma unroll
             for (int q = 0; q < kNC; ++q) acc[q] = 0.0;
             if (valid) index_work(I, st, mode, rows, idx, in, sv, acc);
-            // The record goes to the last work-group with agent-scope atomic stores and
-            // loads, which are coherent across the chiplets' L2 caches on their own; no
-            // full-cache write-back or invalidation is needed for them.
+            // The record goes to the last work-group (elected by a counter) through record
+            // words that carry their own state: agent-scope atomic stores and loads of each
+            // 64-bit word (coherent across the chiplets' L2 caches), a word holding zero until
+            // its value has been written (see rec_put).  So the last work-group needs no
+            // ordering between the records and the counter, and no cache write-back or
+            // invalidation: it waits for each word itself (rec_take).
             double r[kNC];
 #pragma unroll
             for (int q = 0; q < kNC; ++q) r[q] = wave_sum_to63(acc[q]);
             if (lane == 63) {
-                PDOT_GLOBAL double *dst = gp(I.combscal) + (int64_t)E.local * kNB;
+                PDOT_GLOBAL uint64_t *dst = gp((uint64_t *)I.combscal) + (int64_t)E.local * kNB;
 #pragma unroll
-                for (int q = 0; q < kNC; ++q)
-                    __hip_atomic_store(dst + q, r[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int q = 0; q < kNC; ++q) rec_put(dst + q, r[q]);
 #pragma unroll
-                for (int q = 0; q < kNS; ++q)
-                    __hip_atomic_store(dst + kNC + q, tsum[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // those stores (same thread) complete before the counter moves
+                for (int q = 0; q < kNS; ++q) rec_put(dst + kNC + q, tsum[q]);
+                // not needed for correctness: the record stores complete before the counter
+                // moves, so the last work-group normally finds every word on its first load
                 __builtin_amdgcn_s_waitcnt(0);
                 const unsigned prev = __hip_atomic_fetch_add(gp(I.counter), 1u, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
@@ -1181,12 +1263,13 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         double loc[kNB];
 #pragma unroll
         for (int q = 0; q < kNB; ++q) loc[q] = 0.0;
+        bool lost = false;
         for (int c = threadIdx.x; c < I.ncomb; c += kWG) {
-            const PDOT_GLOBAL double *src = gp(I.combscal) + (int64_t)c * kNB;
+            PDOT_GLOBAL uint64_t *src = gp((uint64_t *)I.combscal) + (int64_t)c * kNB;
 #pragma unroll
-            for (int q = 0; q < kNB; ++q)
-                loc[q] += __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < kNB; ++q) loc[q] += rec_take(src + q, lost);
         }
+        if (lost) lost_any = 1;
 #pragma unroll
         for (int q = 0; q < kNB; ++q) loc[q] = wave_sum_to63(loc[q]);
         if (lane == 63) {
@@ -1201,9 +1284,15 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             // the control block is unchanged since this work-group read it (only the last
             // work-group of the instance writes it, below)
             Ctl c = st;
-            control(c, P, mode, tot, tot + kNC, g_red, g_grow);
+            if (lost_any) {   // a record word never arrived: stop the instance, report it
+                c.status = ST_DEVICE;
+                c.mode = M_IDLE;
+            } else {
+                control(c, P, mode, tot, tot + kNC, g_red, g_grow, TraceOut{I.trace, I.trace_cap});
+            }
             *gp(I.ctl) = c;
             __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            lost_any = 0;
         }
         __syncthreads();
     }
@@ -1310,7 +1399,8 @@ void k_resident(const Inst *__restrict__ insts, const int32_t *__restrict__ list
                 for (int q = 0; q < kNB; ++q)
                     tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
                 Ctl c = sctl;
-                control(c, P, mode, tot, tot + kNC, pow(tt, -P.red_exp), pow(tt, -P.grow_exp));
+                control(c, P, mode, tot, tot + kNC, pow(tt, -P.red_exp), pow(tt, -P.grow_exp),
+                        TraceOut{I.trace, I.trace_cap});
                 sctl = c;
             }
             __syncthreads();
@@ -1583,9 +1673,10 @@ __global__ __launch_bounds__(kWG) void k_materialize(TX *__restrict__ dst, int64
                 else if (kind == C_GRID_L1) v = grid_cost<TX, C_GRID_L1>(ia, ib, ja, jb, scale, s32);
                 else if (kind == C_GRID_L2) v = grid_cost<TX, C_GRID_L2>(ia, ib, ja, jb, scale, s32);
                 else v = grid_cost<TX, C_GRID_LINF>(ia, ib, ja, jb, scale, s32);
+            } else if (kind == C_PTS_EU) {
+                v = point_cost<TX, C_PTS_EU>(xs + i * dim, ys + j * dim, dim);
             } else {
-                v = sqdist(xs + i * dim, ys + j * dim, dim);
-                if (kind == C_PTS_EU) v = sqrt(v);
+                v = point_cost<TX, C_PTS_SQ>(xs + i * dim, ys + j * dim, dim);
             }
         }
         dst[e] = (TX)v;

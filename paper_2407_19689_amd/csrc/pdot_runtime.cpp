@@ -29,103 +29,52 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/pdot.h"
+#include "pdot.h"
+#include "pdot_host.h"
 #include "pdot_internal.h"
-
-namespace pdot {
-hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Tile *tiles,
-                       const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
-                       hipEvent_t ev1 = nullptr);
-hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
-                          hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_resident(int fp32, int vec, int cost, const Inst *insts, const int32_t *list,
-                           const int32_t *count, int grid, int32_t budget, hipStream_t s,
-                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,
-                              const double *src, int64_t ldc, const double *xs, const double *ys,
-                              int dim, int side, double scale, hipStream_t s);
-hipError_t launch_round(int cost, const Inst *inst, int ntiles, double *xfeas, hipStream_t s);
-hipError_t launch_widen(const float *src, int64_t m, int64_t n, double *dst, int64_t ld, hipStream_t s);
-}  // namespace pdot
 
 using namespace pdot;
 
+static_assert(sizeof(ot_trace_rec) == sizeof(TraceRec), "trace record layout");
 static_assert((int)OT_COST_GRID_SQEUCLID == (int)C_GRID_SQ && (int)OT_COST_GRID_L1 == (int)C_GRID_L1 &&
                   (int)OT_COST_GRID_L2 == (int)C_GRID_L2 && (int)OT_COST_GRID_LINF == (int)C_GRID_LINF,
               "grid cost kinds share their numbering with the kernels");
 
-namespace {
+namespace pdot {
 
-thread_local std::string g_err;
+// The calling thread's message for ot_last_error: a fixed buffer, so that setting it
+// allocates nothing.
+struct ErrMsg {
+    char buf[1024] = {0};
+    ErrMsg &operator=(const char *s)
+    {
+        snprintf(buf, sizeof buf, "%s", s);
+        return *this;
+    }
+    ErrMsg &operator=(const std::string &s) { return *this = s.c_str(); }
+    void clear() { buf[0] = 0; }
+    bool empty() const { return buf[0] == 0; }
+    const char *c_str() const { return buf; }
+};
+thread_local ErrMsg g_err;
 
-ot_status fail(ot_status st, const std::string &msg)
+ot_status fail(ot_status st, const char *msg)
 {
     g_err = msg;
     return st;
 }
 
-#define HIP_TRY(expr)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(OT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+ot_status fail(ot_status st, const std::string &msg) { return fail(st, msg.c_str()); }
 
-#define OT_TRY(expr)                 \
-    do {                             \
-        ot_status s_ = (expr);       \
-        if (s_ != OT_OK) return s_;  \
-    } while (0)
+// ------------------------------------------------------------------ per-instance layout
 
-constexpr size_t kAlign = 256;
-constexpr int kMaxGrid = 4096;
-constexpr int kMaxGroups = 24;   // precisions x columns-per-lane x cost sources
-// Instances that run on the whole GPU are split by size into lanes; each lane has its own
-// graph and stream, so small instances keep their short slots while large ones run.
-constexpr int kLanes = 3;
-constexpr int64_t kLaneMax[kLanes - 1] = {(int64_t)1 << 18, (int64_t)1 << 24};   // plan entries
-// device counts: per lane the tiles of each variant and the combine entries, then the
-// instances of each resident variant
-constexpr int kLaneCounts = kMaxGroups + 1;
-constexpr int kNumCounts = kLanes * kLaneCounts + kMaxGroups;
+
 
 int lane_of(int64_t elems)
 {
     int l = 0;
     while (l < kLanes - 1 && elems > kLaneMax[l]) ++l;
     return l;
-}
-
-enum { ST_RUNNING = -1 };
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-double now_s()
-{
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// ------------------------------------------------------------------ per-instance layout
-
-struct Layout {
-    int64_t m = 0, n = 0, ld = 0, m_alloc = 0;
-    int fp32 = 1, vec = 4, rows = 64, ncb = 0, nrb = 0, ntiles = 0, ncomb = 0;
-    int cost = C_STORED, dim = 0, side = 0;
-    bool stored = true;
-    bool resident = false;    // one work-group runs the whole instance
-    int lane = 0;             // size lane (instances on the whole GPU)
-    size_t es = 4;
-    size_t off_X[kBufs] = {}, off_C = 0, off_xs = 0, off_ys = 0, off_f = 0, off_g = 0;
-    size_t off_rowv = 0, off_colv = 0, off_rowpart = 0, off_colpart = 0;
-    size_t off_tiles = 0, off_comb = 0, off_counter = 0, off_ctl = 0;
-    size_t bytes = 0;
-};
-
-bool finite_nonneg(const std::vector<double> &v)
-{
-    for (double x : v)
-        if (!std::isfinite(x) || x < 0.0) return false;
-    return true;
 }
 
 // The widest lane (more bytes per load) whose tiles of 16 rows still number about four per
@@ -235,6 +184,9 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     L.off_comb = take(sizeof(double) * (size_t)L.ncomb * kNB);
     L.off_counter = take(sizeof(uint32_t) * 4);
     L.off_ctl = take(sizeof(Ctl));
+    if (pb.trace_cap < 0) return fail(OT_ERR_INVALID, "trace_cap < 0");
+    L.trace_cap = pb.trace ? pb.trace_cap : 0;
+    L.off_trace = L.trace_cap ? take(sizeof(TraceRec) * (size_t)L.trace_cap) : 0;
     L.bytes = off;
     return OT_OK;
 }
@@ -252,6 +204,7 @@ Prm device_params(const ot_params &p, double tol)
     d.avg_weighting = p.avg_weighting;
     d.pwu = p.primal_weight_update;
     d.output = p.output;
+    d.verify_retries = p.verify_retries;
     d.beta_suff = p.beta_sufficient;
     d.beta_nec = p.beta_necessary;
     d.beta_art = p.beta_artificial;
@@ -266,7 +219,8 @@ Prm device_params(const ot_params &p, double tol)
 ot_status check_params(const ot_params &prm)
 {
     if (!(prm.tol > 0.0)) return fail(OT_ERR_INVALID, "tol must be > 0");
-    if (prm.max_iters < 0 || prm.max_passes < 0) return fail(OT_ERR_INVALID, "negative limits");
+    if (prm.max_iters < 0 || prm.max_passes < 0 || prm.verify_retries < 0)
+        return fail(OT_ERR_INVALID, "negative limits");
     return OT_OK;
 }
 
@@ -279,6 +233,134 @@ bool is_device_ptr(const void *p)
         return false;
     }
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+
+
+void init_inst(const Layout &l, char *b, double scale, const ot_params &prm, double tol, Inst &I)
+{
+    memset(&I, 0, sizeof(I));
+    I.m = l.m;
+    I.n = l.n;
+    I.ld = l.ld;
+    I.m_alloc = l.m_alloc;
+    I.cost = l.cost;
+    I.dim = l.dim;
+    I.side = l.side;
+    I.vec = l.vec;
+    I.rows = l.rows;
+    I.ncb = l.ncb;
+    I.nrb = l.nrb;
+    I.ntiles = l.ntiles;
+    I.ncomb = l.ncomb;
+    I.scale = scale;
+    for (int k = 0; k < kBufs; ++k) I.X[k] = b + l.off_X[k];
+    I.C = l.stored ? (const void *)(b + l.off_C) : nullptr;
+    I.xs = l.dim ? (const double *)(b + l.off_xs) : nullptr;
+    I.ys = l.dim ? (const double *)(b + l.off_ys) : nullptr;
+    I.f = (const double *)(b + l.off_f);
+    I.g = (const double *)(b + l.off_g);
+    double *rv = (double *)(b + l.off_rowv);
+    double *cv = (double *)(b + l.off_colv);
+    const int64_t m = l.m, n = l.n;
+    I.p[0] = rv + 0 * m; I.p[1] = rv + 1 * m; I.pb[0] = rv + 2 * m; I.pb[1] = rv + 3 * m;
+    I.pa = rv + 4 * m; I.rs[0] = rv + 5 * m; I.rs[1] = rv + 6 * m; I.rsb = rv + 7 * m;
+    I.q[0] = cv + 0 * n; I.q[1] = cv + 1 * n; I.qb[0] = cv + 2 * n; I.qb[1] = cv + 3 * n;
+    I.qa = cv + 4 * n; I.cs[0] = cv + 5 * n; I.cs[1] = cv + 6 * n; I.csb = cv + 7 * n;
+    I.rowpart = (double *)(b + l.off_rowpart);
+    I.colpart = (double *)(b + l.off_colpart);
+    I.tilescal = (double *)(b + l.off_tiles);
+    I.combscal = (double *)(b + l.off_comb);
+    I.counter = (uint32_t *)(b + l.off_counter);
+    I.ctl = (Ctl *)(b + l.off_ctl);
+    I.trace = l.trace_cap ? (TraceRec *)(b + l.off_trace) : nullptr;
+    I.trace_cap = l.trace_cap;
+    I.prm = device_params(prm, tol);
+}
+
+void init_ctl(const Layout &l, const ot_params &prm, double tol, Ctl &c)
+{
+    memset(&c, 0, sizeof(c));
+    c.mode = M_INIT;
+    c.status = ST_RUNNING;
+    for (int k = 0; k < kBufs; ++k) c.xr[k] = k;
+    c.eta = prm.eta0 > 0.0 ? prm.eta0 : 1.0 / std::sqrt((double)(l.m + l.n));
+    c.omega = prm.omega0 > 0.0 ? prm.omega0 : 1.0;
+    c.tol_eff = tol;
+}
+
+void fill_result(const Layout &l, const Ctl &c, ot_status st, ot_result &o)
+{
+    memset(&o, 0, sizeof(o));
+    o.status = st;
+    o.returned_average = c.ret_avg;
+    o.iterations = c.T;
+    o.passes = c.passes;
+    o.restarts = c.restarts;
+    o.kernel_passes = c.kpasses;
+    o.objective = c.r_obj;
+    o.dual_objective = c.r_dobj;
+    o.rel_primal = c.r_relP;
+    o.rel_dual = c.r_relD;
+    o.rel_gap = c.r_relG;
+    o.rel_kkt = c.r_kkt;
+    o.eta = c.eta;
+    o.omega = c.omega;
+    // algorithmic bytes per element of each pass kind (plan element size b, cost
+    // element size bc, 0 when regenerated): start-point KKT reads C; a trial or full
+    // pass reads X and C and writes X+, and when it folds two iterates it also reads
+    // the average and writes the next one; the restart pass reads two plans;
+    // verification reads X and C; the fold pass reads two plans and writes one
+    const double b = (double)l.es, bc = l.stored ? (double)l.es : 0.0;
+    const double per[kModes] = {0.0, bc, 2 * b + bc, 2 * b + bc, 2 * b, b + bc, 3 * b};
+    const double elems = (double)l.m * (double)l.n;
+    double bytes = 2 * b * elems * (double)c.fold2;
+    for (int k = 0; k < kModes; ++k) {
+        o.mode_passes[k] = c.mcount[k];
+        bytes += per[k] * elems * (double)c.mcount[k];
+    }
+    o.avg_fold_passes = c.fold2;
+    o.pass_bytes = bytes;
+    o.verify_retries = c.verify_fails;
+    o.kkt_estimate = c.K_cand;
+    for (int q = 0; q < 3; ++q) o.estimate_parts[q] = c.e_rel[q];
+    o.estimate_objective = c.e_obj;
+    o.trace_len = std::min<int64_t>(c.ntrace, l.trace_cap);
+}
+
+}  // namespace pdot
+
+namespace {
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(OT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define OT_TRY(expr)                 \
+    do {                             \
+        ot_status s_ = (expr);       \
+        if (s_ != OT_OK) return s_;  \
+    } while (0)
+
+constexpr int kMaxGroups = 24;   // precisions x columns-per-lane x cost sources
+// device counts: per lane the tiles of each variant and the combine entries, then the
+// instances of each resident variant
+constexpr int kLaneCounts = kMaxGroups + 1;
+constexpr int kNumCounts = kLanes * kLaneCounts + kMaxGroups;
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool finite_nonneg(const std::vector<double> &v)
+{
+    for (double x : v)
+        if (!std::isfinite(x) || x < 0.0) return false;
+    return true;
 }
 
 // A non-blocking stream of the calling thread for small host fetches: the legacy stream
@@ -619,42 +701,9 @@ public:
         ot_status copy_st = OT_OK;
         if (ist == OT_OK || ist == OT_NOT_CONVERGED) copy_st = copy_outputs(r, c);
         ot_result &o = r.res;
-        memset(&o, 0, sizeof(o));
-        o.status = copy_st != OT_OK ? copy_st : ist;
-        o.returned_average = c.ret_avg;
-        o.iterations = c.T;
-        o.passes = c.passes;
-        o.restarts = c.restarts;
-        o.kernel_passes = c.kpasses;
-        o.objective = c.r_obj;
-        o.dual_objective = c.r_dobj;
-        o.rel_primal = c.r_relP;
-        o.rel_dual = c.r_relD;
-        o.rel_gap = c.r_relG;
-        o.rel_kkt = c.r_kkt;
-        o.eta = c.eta;
-        o.omega = c.omega;
-        // algorithmic bytes per element of each pass kind (plan element size b, cost
-        // element size bc, 0 when regenerated): start-point KKT reads C; a trial or full
-        // pass reads X and C and writes X+, and when it folds two iterates it also reads
-        // the average and writes the next one; the restart pass reads two plans;
-        // verification reads X and C; the fold pass reads two plans and writes one
-        const double b = (double)l.es, bc = l.stored ? (double)l.es : 0.0;
-        const double per[kModes] = {0.0, bc, 2 * b + bc, 2 * b + bc, 2 * b, b + bc, 3 * b};
-        const double elems = (double)l.m * (double)l.n;
-        double bytes = 2 * b * elems * (double)c.fold2;
-        for (int k = 0; k < kModes; ++k) {
-            o.mode_passes[k] = c.mcount[k];
-            bytes += per[k] * elems * (double)c.mcount[k];
-        }
-        o.avg_fold_passes = c.fold2;
-        o.pass_bytes = bytes;
+        fill_result(l, c, copy_st != OT_OK ? copy_st : ist, o);
         o.pass_ms = r.pass_ms;
         o.combine_ms = r.comb_ms;
-        o.verify_retries = c.verify_fails;
-        o.kkt_estimate = c.K_cand;
-        for (int q = 0; q < 3; ++q) o.estimate_parts[q] = c.e_rel[q];
-        o.estimate_objective = c.e_obj;
         (void)I;
         r.done = true;
         arena_.release(r.off, l.bytes);
@@ -778,6 +827,9 @@ private:
         const double *qr = c.ret_avg ? I.qb[c.pbv] : I.q[c.pv];
         if (r.prob.u_out) HIP_TRY(hipMemcpyAsync(r.prob.u_out, pr, sizeof(double) * l.m, hipMemcpyDefault, s_));
         if (r.prob.v_out) HIP_TRY(hipMemcpyAsync(r.prob.v_out, qr, sizeof(double) * l.n, hipMemcpyDefault, s_));
+        const int64_t nt = std::min<int64_t>(c.ntrace, l.trace_cap);
+        if (nt > 0)
+            HIP_TRY(hipMemcpyAsync(r.prob.trace, I.trace, sizeof(TraceRec) * (size_t)nt, hipMemcpyDefault, s_));
         HIP_TRY(hipStreamSynchronize(s_));
         return OT_OK;
     }
@@ -788,41 +840,8 @@ private:
         const ot_problem &pb = r.prob;
         char *b = base_ + r.off;
         Inst &I = r.I;
-        memset(&I, 0, sizeof(I));
-        I.m = l.m;
-        I.n = l.n;
-        I.ld = l.ld;
-        I.m_alloc = l.m_alloc;
-        I.cost = l.cost;
-        I.dim = l.dim;
-        I.side = l.side;
-        I.vec = l.vec;
-        I.rows = l.rows;
-        I.ncb = l.ncb;
-        I.nrb = l.nrb;
-        I.ntiles = l.ntiles;
-        I.ncomb = l.ncomb;
-        I.scale = pb.cost.scale;
-        for (int k = 0; k < kBufs; ++k) I.X[k] = b + l.off_X[k];
-        I.C = l.stored ? (const void *)(b + l.off_C) : nullptr;
-        I.xs = l.dim ? (const double *)(b + l.off_xs) : nullptr;
-        I.ys = l.dim ? (const double *)(b + l.off_ys) : nullptr;
-        I.f = (const double *)(b + l.off_f);
-        I.g = (const double *)(b + l.off_g);
-        double *rv = (double *)(b + l.off_rowv);
-        double *cv = (double *)(b + l.off_colv);
+        init_inst(l, b, pb.cost.scale, prm_, r.tol, I);
         const int64_t m = l.m, n = l.n;
-        I.p[0] = rv + 0 * m; I.p[1] = rv + 1 * m; I.pb[0] = rv + 2 * m; I.pb[1] = rv + 3 * m;
-        I.pa = rv + 4 * m; I.rs[0] = rv + 5 * m; I.rs[1] = rv + 6 * m; I.rsb = rv + 7 * m;
-        I.q[0] = cv + 0 * n; I.q[1] = cv + 1 * n; I.qb[0] = cv + 2 * n; I.qb[1] = cv + 3 * n;
-        I.qa = cv + 4 * n; I.cs[0] = cv + 5 * n; I.cs[1] = cv + 6 * n; I.csb = cv + 7 * n;
-        I.rowpart = (double *)(b + l.off_rowpart);
-        I.colpart = (double *)(b + l.off_colpart);
-        I.tilescal = (double *)(b + l.off_tiles);
-        I.combscal = (double *)(b + l.off_comb);
-        I.counter = (uint32_t *)(b + l.off_counter);
-        I.ctl = (Ctl *)(b + l.off_ctl);
-        I.prm = device_params(prm_, r.tol);
 
         HIP_TRY(hipMemsetAsync(b, 0, l.bytes, s_));
         const HostData *h = r.host.get();
@@ -865,13 +884,7 @@ private:
             if (tmp) HIP_TRY(hipFreeAsync(tmp, s_));
         }
         Ctl c;
-        memset(&c, 0, sizeof(c));
-        c.mode = M_INIT;
-        c.status = ST_RUNNING;
-        for (int k = 0; k < kBufs; ++k) c.xr[k] = k;
-        c.eta = prm_.eta0 > 0.0 ? prm_.eta0 : 1.0 / std::sqrt((double)(m + n));
-        c.omega = prm_.omega0 > 0.0 ? prm_.omega0 : 1.0;
-        c.tol_eff = r.tol;
+        init_ctl(l, prm_, r.tol, c);
         h_ctl_[r.slot] = c;
         HIP_TRY(hipMemcpyAsync(I.ctl, &h_ctl_[r.slot], sizeof(Ctl), hipMemcpyHostToDevice, s_));
         HIP_TRY(hipMemcpyAsync(d_insts() + r.slot, &I, sizeof(Inst), hipMemcpyHostToDevice, s_));
@@ -1106,7 +1119,7 @@ ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, P
     std::vector<std::pair<std::tuple<int, int, int, int>, int64_t>> per;
     for (int i = 0; i < count; ++i) {
         ot_status st = plan_instance(probs[i], prm, P.L[i]);
-        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err.c_str());
         const Layout &l = P.L[i];
         if (l.resident) continue;
         combs[l.lane] += l.ncomb;
@@ -1150,7 +1163,7 @@ ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot
         OT_TRY(fetch_host(probs[i].f, (size_t)probs[i].m, fh));
         OT_TRY(fetch_host(probs[i].g, (size_t)probs[i].n, gh));
         ot_status st = validate_marginals(fh, gh);
-        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err);
+        if (st != OT_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_err.c_str());
         reqs[i].L = P.L[i];
         reqs[i].prob = probs[i];
         reqs[i].tol = probs[i].tol > 0.0 ? probs[i].tol : prm.tol;
@@ -1160,7 +1173,7 @@ ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot
     for (int i = 0; i < count; ++i) {
         ot_status st = E.admit(reqs[i]);
         if (st != OT_OK)
-            return fail(st == OT_ERR_BUSY ? OT_ERR_OOM : st, "instance " + std::to_string(i) + ": " + g_err);
+            return fail(st == OT_ERR_BUSY ? OT_ERR_OOM : st, "instance " + std::to_string(i) + ": " + g_err.c_str());
     }
     bool stop_sent = false;
     ot_status hard = OT_OK;
@@ -1290,7 +1303,7 @@ struct ot_server {
             const ot_status st = E.run_block(cfg.params.graph_slots, cfg.block_ms > 0 ? cfg.block_ms : 2.0);
             if (st != OT_OK) {
                 std::lock_guard<std::mutex> lk(mu);
-                thread_error = g_err;
+                thread_error = g_err.c_str();
                 for (auto &r : running) {
                     r->res.status = st;
                     r->t_done = now_s() - t0;
@@ -1362,6 +1375,7 @@ void ot_params_default(ot_params *p)
     p->step_growth_exp = 0.6;
     p->tile_vec = 0;
     p->tile_rows = 0;
+    p->verify_retries = 8;
 }
 
 size_t ot_workspace_size(const ot_problem *prob, const ot_params *prm)
@@ -1405,6 +1419,8 @@ ot_status ot_round(const ot_problem *prob, int32_t precision, const void *X, con
     pb.X_out = nullptr;
     pb.u_out = nullptr;
     pb.v_out = nullptr;
+    pb.trace = nullptr;
+    pb.trace_cap = 0;
     Planned P;
     OT_TRY(plan_fixed(&pb, 1, prm, P));
     std::vector<double> fh, gh;

@@ -38,13 +38,13 @@ def test_ctypes_structs_match_c_layout(tmp_path):
     cls = {"ot_cost": P.OtCost, "ot_problem": P.OtProblem, "ot_params": P.OtParams,
            "ot_result": P.OtResult, "ot_server_cfg": P.OtServerCfg,
            "ot_completion": P.OtCompletion, "ot_server_stats": P.OtServerStats,
-           "ot_bracket": P.OtBracket}
+           "ot_bracket": P.OtBracket, "ot_trace_rec": P.OtTraceRec}
     fields = {st: [f for f, _ in c._fields_] for st, c in cls.items()}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){']
     for st, fl in fields.items():
         lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
         for f in fl:
-            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f.rstrip("_")}));')
     lines.append("return 0;}")
     src.write_text("\n".join(lines))
     exe = tmp_path / "layout"
@@ -66,6 +66,7 @@ def test_defaults_are_the_paper_constants():
     assert p.tol == 1e-4 and p.time_limit_s == 3600.0
     assert p.precision == P.OT_PREC_FP32 and p.kkt_mode == 0 and p.restart_rule == 0
     assert p.engine == 0          # small instances resident, large ones on the whole GPU
+    assert p.verify_retries == 8
 
 
 def _dense(m, n):
@@ -75,7 +76,7 @@ def _dense(m, n):
 
 
 @pytest.mark.parametrize("case", ["m0", "n0", "tol", "ldc", "rows", "vec", "grid", "kind",
-                                  "dim", "prec", "engine"])
+                                  "dim", "prec", "engine", "retries", "trace"])
 def test_invalid_problems_rejected_before_device_work(case):
     f, g, C = _dense(4, 5)
     kw = {}
@@ -103,6 +104,11 @@ def test_invalid_problems_rejected_before_device_work(case):
         kw["precision"] = 7
     elif case == "engine":
         kw["engine"] = 3
+    elif case == "retries":
+        kw["verify_retries"] = -1
+    elif case == "trace":
+        pr = P.problem(P.OT_COST_DENSE, 4, 5, f, g, C=C, trace_cap=4)
+        pr.raw.trace_cap = -1
     st, _ = P.ot_solve(pr, P.params(**kw))
     assert st == P.OT_ERR_INVALID, (case, st, P.ot_last_error())
     assert P.ot_last_error()

@@ -35,6 +35,7 @@ import math
 import numpy as np
 import pytest
 
+from tests.trace_walk import walk_traces
 from workloads import generators as gen
 
 # PDLP's step-size constants (Applegate et al. 2021), cited by Section 5.
@@ -195,23 +196,10 @@ def oracle_kwargs(ref):
                 primal_weight_update=1 if ref.pwu else 0)
 
 
-def _rel(a, b):
-    return abs(a - b) / abs(b) if b != 0 else abs(a)
-
-
 def compare(orc, C, f, g, iters=300, tol=1e-12, drift_cap=1e-6, **kw):
-    """Run both on the same instance and walk the two traces together.
-
-    The sides sum in different orders.  With a constant step the difference stays at the
-    rounding level.  With the adaptive step it grows: the step bound's denominator
-    dy^T A dx and the duality gap are differences of nearly equal sums, and the step rule
-    feeds the bound back into eta, so the two trajectories separate by roughly a factor
-    1000 every 60 iterations (from about 1e-15), and once the separation reaches the
-    margins of the comparisons the decisions may part.  So the walk covers the prefix in
-    which the traced scalars (eta used, omega, both KKT values) still agree to drift_cap;
-    over that prefix every decision (pass and iteration numbers, accepted or rejected,
-    restart and its condition, candidate side) must be identical, and eta_bar must agree
-    where it can decide anything.  Returns the compared reference entries."""
+    """Run both on the same instance and walk the two traces together (walk_traces): over
+    the prefix in which their scalars agree to drift_cap every decision must be identical.
+    Returns the compared reference entries and the final states."""
     ref = ExplicitPDHG(C, f, g, **kw)
     okw = oracle_kwargs(ref)
     okw["eta0"] = ref.eta
@@ -219,22 +207,7 @@ def compare(orc, C, f, g, iters=300, tol=1e-12, drift_cap=1e-6, **kw):
     X, p, q, res, tr = orc.solve(C, f, g, tol=tol, max_iters=iters, trace_cap=100000,
                                  nthreads=1, step_reduction_exp=0.3, step_growth_exp=0.6,
                                  **okw)
-    compared = []
-    for a, b in zip(tr, tr_ref):
-        keys = ("eta_used", "omega") + (("k_cur", "k_avg") if b["accepted"] else ())
-        if max(_rel(a[k], b[k]) for k in keys) > drift_cap:
-            break
-        for key in ("pass_", "iter", "accepted", "restart", "cand_avg"):
-            ka = "pass" if key == "pass_" else key
-            assert a[ka] == b[key], (key, a, b)
-        va, vb = a["eta_bar"], b["eta_bar"]
-        if math.isinf(vb):
-            assert math.isinf(va), (a, b)
-        elif vb <= 10.0 * b["eta_used"]:
-            assert _rel(va, vb) <= 100.0 * drift_cap, (a, b)
-        else:   # far above the step in use it decides nothing; its denominator is noise
-            assert va > 5.0 * b["eta_used"], (a, b)
-        compared.append(b)
+    compared = walk_traces(tr, tr_ref, drift_cap)
     if len(compared) == len(tr_ref):
         assert len(tr) == len(tr_ref)
         assert res["iterations"] == info["T"] and res["restarts"] == info["restarts"]

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import paper_2407_19689_amd as P
+from tests.test_gpu_parity import assert_matches_oracle
 from workloads import generators as gen
 
 torch = pytest.importorskip("torch")
@@ -71,6 +72,7 @@ def test_server_results_equal_solo_and_overlap():
         assert d["objective"] == res["objective"]
         assert np.array_equal(out["X"].cpu().numpy(), solo["X"].cpu().numpy())
         assert np.array_equal(out["u"].cpu().numpy(), solo["u"].cpu().numpy())
+        assert_matches_oracle(inst, d, out, P.OT_PREC_FP32)
 
 
 def test_server_admission_respects_the_memory_budget():
