@@ -248,6 +248,24 @@ ot_status ot_solve(const ot_problem *prob, const ot_params *prm, ot_result *res,
 ot_status ot_solve_batch(const ot_problem *probs, int32_t count, const ot_params *prm,
                          ot_result *res, void *stream);
 
+/* ---- solving without allocation ------------------------------------------------------
+ *
+ * For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): ot_solve with its whole workspace -- plan buffers,
+ * cost, coordinates, vectors, partial sums, control block and the launch tables -- in a
+ * static device array of OT_NOALLOC_MAX_BYTES that the library holds on every GPU it runs
+ * on until the process ends.  The call allocates nothing (no device, pinned or heap memory,
+ * no stream, event or graph): it launches the same kernels as ot_solve directly on
+ * `stream` (NULL: the null stream) and returns when the results are in the outputs, which
+ * equal ot_solve's for the same problem and parameters bit for bit.  Every call on a GPU
+ * uses that GPU's one array, so calls that overlap on one GPU race: serialise them per
+ * device.  The array keeps the last call's contents; a call clears what it uses first.
+ * ot_params.profile is ignored.  OT_ERR_OOM (with the size in ot_last_error()) when the
+ * problem needs more than OT_NOALLOC_MAX_BYTES; otherwise the statuses of ot_solve. */
+#define OT_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+ot_status ot_solve_noalloc(const ot_problem *prob, const ot_params *prm, ot_result *res,
+                           void *stream);
+
 /* ---- rounding to a feasible plan and the certified bracket ---------------------------
  *
  * Algorithm 3 (Section 3.2; Altschuler et al.'s rounding) maps an approximately feasible

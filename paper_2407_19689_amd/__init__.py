@@ -18,11 +18,12 @@ from ._abi import (  # noqa: F401
     OT_OK, OT_ERR_INVALID, OT_ERR_OOM, OT_ERR_DEVICE, OT_NOT_CONVERGED, OT_ERR_NUMERIC,
     OT_ERR_BUSY, OT_PREC_FP64, OT_PREC_FP32, OT_COST_DENSE, OT_COST_POINTS_SQEUCLID,
     OT_COST_POINTS_EUCLID, OT_COST_GRID_SQEUCLID, OT_COST_GRID_L1, OT_COST_GRID_L2,
-    OT_COST_GRID_LINF, OtCost, OtParams, OtProblem, OtResult, OtTraceRec,
+    OT_COST_GRID_LINF, OT_NOALLOC_MAX_BYTES, OtCost, OtParams, OtProblem, OtResult, OtTraceRec,
     OtServerCfg, OtCompletion, OtServerStats, OtBracket, STATUS_NAMES,
 )
 
-__all__ = ["ot_params_default", "ot_workspace_size", "ot_solve", "ot_solve_batch", "ot_round",
+__all__ = ["ot_params_default", "ot_workspace_size", "ot_solve", "ot_solve_noalloc",
+           "ot_solve_batch", "ot_round",
            "ot_last_error", "ot_version", "ot_server_create", "ot_server_submit",
            "ot_server_poll", "ot_server_drain", "ot_server_get_stats", "ot_server_destroy",
            "params", "problem", "solve_instance", "problem_from_instance", "Server"]
@@ -138,6 +139,14 @@ def ot_solve(prob: Problem, prm: OtParams, workspace=None, stream=None):
             else workspace.nbytes
     st = _abi.load().ot_solve(ct.byref(prob.raw), ct.byref(prm), ct.byref(res), ws, nbytes,
                               stream)
+    return int(st), res
+
+
+def ot_solve_noalloc(prob: Problem, prm: OtParams, stream=None):
+    """ot_solve on the library's static device array (no allocation).  Returns
+    (status, OtResult)."""
+    res = OtResult()
+    st = _abi.load().ot_solve_noalloc(ct.byref(prob.raw), ct.byref(prm), ct.byref(res), stream)
     return int(st), res
 
 

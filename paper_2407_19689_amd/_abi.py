@@ -34,6 +34,9 @@ OT_COST_GRID_L1 = 4
 OT_COST_GRID_L2 = 5
 OT_COST_GRID_LINF = 6
 
+# bytes of the static device array behind ot_solve_noalloc
+OT_NOALLOC_MAX_BYTES = 128 << 20
+
 _D = ct.POINTER(ct.c_double)
 
 
@@ -207,6 +210,8 @@ SIGNATURES = {
     "ot_workspace_size": (ct.c_size_t, [ct.POINTER(OtProblem), ct.POINTER(OtParams)]),
     "ot_solve": (ct.c_int, [ct.POINTER(OtProblem), ct.POINTER(OtParams), ct.POINTER(OtResult),
                             ct.c_void_p, ct.c_size_t, ct.c_void_p]),
+    "ot_solve_noalloc": (ct.c_int, [ct.POINTER(OtProblem), ct.POINTER(OtParams), ct.POINTER(OtResult),
+                                    ct.c_void_p]),
     "ot_solve_batch": (ct.c_int, [ct.POINTER(OtProblem), ct.c_int32, ct.POINTER(OtParams),
                                   ct.POINTER(OtResult), ct.c_void_p]),
     "ot_round": (ct.c_int, [ct.POINTER(OtProblem), ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p,

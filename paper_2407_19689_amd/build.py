@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdot.so")
-SOURCES = ["pdot_kernels.hip", "pdot_runtime.cpp"]
+SOURCES = ["pdot_kernels.hip", "pdot_runtime.cpp", "pdot_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

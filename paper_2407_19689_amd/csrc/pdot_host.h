@@ -1,5 +1,6 @@
-// Host-side pieces of the runtime (pdot_runtime.cpp): kernel launchers, the per-instance
-// workspace layout, parameter checks and the filling of results.  Not part of the public ABI (include/pdot.h is).
+// Host-side pieces shared by the runtime (pdot_runtime.cpp) and the no-allocation entry
+// point (pdot_noalloc.hip): kernel launchers, the per-instance workspace layout, parameter
+// checks and the filling of results.  Not part of the public ABI (include/pdot.h is).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -26,6 +27,13 @@ hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t
                               int dim, int side, double scale, hipStream_t s);
 hipError_t launch_round(int cost, const Inst *inst, int ntiles, double *xfeas, hipStream_t s);
 hipError_t launch_widen(const float *src, int64_t m, int64_t n, double *dst, int64_t ld, hipStream_t s);
+// Zero `bytes` (a multiple of 8) at a 256-byte aligned device address (a kernel, not a
+// memset node, so that it behaves alike inside and outside graph capture).
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t s);
+// Tile table (row block, column band of every tile, in row-major order), combine table
+// (row slices, then column slices) and the two counts of one instance in slot 0.
+hipError_t launch_tables(Tile *tiles, int ntiles, int ncb, CombEntry *combs, int64_t m, int64_t n,
+                         int32_t *counts, hipStream_t s);
 
 // ---- sizes and limits
 constexpr size_t kAlign = 256;

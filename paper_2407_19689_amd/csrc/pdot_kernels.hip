@@ -1683,6 +1683,34 @@ __global__ __launch_bounds__(kWG) void k_materialize(TX *__restrict__ dst, int64
     }
 }
 
+// Zero fill (8-byte words) of a workspace region.
+__global__ __launch_bounds__(kWG) void k_zero(uint64_t *__restrict__ dst, int64_t words)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x; e < words; e += (int64_t)gridDim.x * kWG)
+        dst[e] = 0;
+}
+
+// The tile and combine tables of one instance in slot 0 (the order the runtime uses: tiles
+// by row block then column band, combine entries for the row slices then the column
+// slices), the two counts, and a one-entry resident list {0} with its count.
+__global__ __launch_bounds__(kWG) void k_tables(Tile *__restrict__ tiles, int ntiles, int ncb,
+                                                CombEntry *__restrict__ combs, int nrows, int ncomb,
+                                                int32_t *__restrict__ counts)
+{
+    const int stride = gridDim.x * kWG;
+    for (int t = blockIdx.x * kWG + threadIdx.x; t < ntiles; t += stride)
+        tiles[t] = Tile{0, t / ncb, t % ncb, t};
+    for (int e = blockIdx.x * kWG + threadIdx.x; e < ncomb; e += stride)
+        combs[e] = e < nrows ? CombEntry{0, 0, e * kCombEntries, e}
+                             : CombEntry{0, 1, (e - nrows) * kCombEntries, e};
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        counts[0] = ntiles;
+        counts[1] = ncomb;
+        counts[2] = 1;
+        counts[3] = 0;
+    }
+}
+
 }  // namespace pdot
 
 // ------------------------------------------------------------------ launchers (host)
@@ -1847,6 +1875,30 @@ hipError_t launch_round(int cost, const Inst *inst, int ntiles, double *xfeas, h
     case C_GRID_LINF: return launch_round_cost<C_GRID_LINF>(inst, xfeas, grid, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_zero(void *dst, size_t bytes, hipStream_t s)
+{
+    const int64_t words = (int64_t)(bytes / 8);
+    if (words <= 0) return hipSuccess;
+    int64_t blocks = (words + kWG - 1) / kWG;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(kWG), 0, s, (uint64_t *)dst, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(Tile *tiles, int ntiles, int ncb, CombEntry *combs, int64_t m, int64_t n,
+                         int32_t *counts, hipStream_t s)
+{
+    const int nrows = (int)((m + kCombEntries - 1) / kCombEntries);
+    const int ncomb = nrows + (int)((n + kCombEntries - 1) / kCombEntries);
+    const int most = ntiles > ncomb ? ntiles : ncomb;
+    int blocks = (most + kWG - 1) / kWG;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_tables, dim3(blocks), dim3(kWG), 0, s, tiles, ntiles, ncb, combs, nrows, ncomb,
+                       counts);
+    return hipGetLastError();
 }
 
 hipError_t launch_materialize(int fp32, void *dst, int64_t m, int64_t n, int64_t ld, int kind,

@@ -43,7 +43,7 @@ static_assert((int)OT_COST_GRID_SQEUCLID == (int)C_GRID_SQ && (int)OT_COST_GRID_
 namespace pdot {
 
 // The calling thread's message for ot_last_error: a fixed buffer, so that setting it
-// allocates nothing.
+// allocates nothing (the no-allocation entry point sets it too).
 struct ErrMsg {
     char buf[1024] = {0};
     ErrMsg &operator=(const char *s)
