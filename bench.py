@@ -7,17 +7,25 @@ to relative KKT 1e-6.  One timed step is one complete solve (every iteration of 
 the whole hot path: primal step, sums, dual step, averaging, KKT, restart and step-size
 checks).  `value` is accepted PDHG iterations per second over the timed solves.
 
-Also reported: time to 1e-4 and 1e-6 (also averaged over five images), the
-stored-FP32-cost and plain-FP64 forms, the smaller workloads (64 points, 1024 x 1024
-grid) in both precisions, the rounded plan's certified bracket, the streaming kernel
-against the HBM roofline (durations from the events stamped by every pass launch of one
-profiled solve, launched in back-to-back blocks of 16 slots), a synthetic suite with the
-paper's reporting, a batch of 256 uneven instances in one ot_solve_batch (makespan,
-completion p50/p99, against solving a subset one by one), a continuous-batching server
-fed a Poisson request stream (latency p50/p99, solves/s), and the FP64 CPU oracle timed
-on a bounded sample.
+Also reported: time to 1e-4 and 1e-6 (also averaged over five images), each result's
+objective error against the FP64 oracle's objective at tol 1e-8 (stored by
+tests/golden/make_golden.py), the stored-FP32-cost and plain-FP64 forms, the smaller
+workloads (64 points, 1024 x 1024 grid) in both precisions, Algorithm 2 as printed against
+the Section 5 rules on the 1024 grid, the rounded plan's certified bracket, the streaming
+kernel against the HBM roofline (durations from the events stamped by every pass launch of
+one profiled solve, launched in back-to-back blocks of 16 slots; a plain device copy of the
+same bytes as the practical ceiling; the same measurement at m = n = 8100, where nothing
+fits the Infinity Cache), a synthetic suite with the paper's reporting at 32x32, 64x64 and
+128x128, a batch of 256 uneven instances in one ot_solve_batch (makespan, completion
+p50/p99, against solving a subset one by one), a continuous-batching server fed 200
+requests of the Poisson stream at a fixed rate (latency p50/p99, solves/s), and the FP64
+CPU oracle (a bounded sample at 4096, its whole solve of the 1024 grid to 1e-6).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
-       [--no-suite] [--no-batch] [--no-serving] [--serve-requests N]
+       [--no-suite] [--suite-sizes 32,64,128] [--no-batch] [--no-serving]
+       [--serve-requests N] [--serve-rate R] [--traffic-probe] [--beyond-cache-probe]
+       [--batch-probe] [--summarize-traffic FETCH_DIR WRITE_DIR PROBE_LOG]
+       [--summarize-trace STATS_CSV OUT_MD TITLE COMMAND]
+       [--summarize-counters CSV_GLOB OUT_MD TITLE COMMAND...]
 """
 import argparse
 import json
@@ -59,6 +67,40 @@ def kernel_sha():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
+def beyond_cache(probe=False):
+    """The streaming pass where nothing fits the 256 MB Infinity Cache: the 90 x 90 grid
+    pair (m = n = 8100, FP32 plan, cost regenerated; 262 MB per plan), 300 iterations of a
+    profiled solve (every pass launch timed by its own events); with probe=True (the
+    workload of the committed rocprofv3 summaries) it prints the launch mix instead."""
+    import torch
+    import paper_2407_19689_amd as P
+    from workloads import generators as gen
+    inst = gen.grid_pair(201, 90)
+    prm = P.params(tol=1e-12, precision=P.OT_PREC_FP32, max_iters=300, time_limit_s=60.0,
+                   profile=0 if probe else 1)
+    pr, _ = P.problem_from_instance(inst, precision=P.OT_PREC_FP32, want_plan=False)
+    st, r = P.ot_solve(pr, prm)
+    torch.cuda.synchronize()
+    launches = sum(r.mode_passes)
+    if probe:
+        print(json.dumps({"probe": "beyond_cache", "launches": launches,
+                          "algorithmic_bytes_per_launch": r.pass_bytes / launches,
+                          "mode_passes": list(r.mode_passes)}), flush=True)
+        return None
+    avg_ms = r.pass_ms / launches
+    avg_bytes = r.pass_bytes / launches
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    ceiling = copy_ceiling(avg_bytes)
+    out = {"workload": "two 90x90 blob images (seed 201), m=n=8100, FP32 plan, cost regenerated, "
+                       "300 iterations", "avg_launch_us": round(avg_ms * 1e3, 2),
+           "algorithmic_bytes_per_launch": round(avg_bytes), "achieved_GBps": round(achieved, 1),
+           "frac_of_peak": round(achieved / HBM_PEAK_GBS, 4),
+           "copy_ceiling_GBps": round(ceiling, 1), "frac_of_copy_ceiling": round(achieved / ceiling, 4),
+           "combine_avg_us": round(r.combine_ms / launches * 1e3, 2)}
+    log(f"beyond cache (8100): {out}")
+    return out
+
+
 def traffic_probe():
     """Workload for the two counter runs (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE): a
     plain 1 GiB device copy (calibration) and 300 iterations of the benchmark solve."""
@@ -79,6 +121,14 @@ def traffic_probe():
     print(json.dumps({"probe": "traffic", "launches": launches,
                       "algorithmic_bytes_per_launch": r.pass_bytes / launches,
                       "mode_passes": list(r.mode_passes)}), flush=True)
+
+
+# the counter probes and where their summaries go
+PROBES = {
+    "traffic": ("k_pass (m=n=4096 grid, FP32 plan, cost regenerated)", "--traffic-probe", TRAFFIC_FILE),
+    "beyond_cache": ("k_pass (m=n=8100 grid, FP32 plan, cost regenerated; nothing fits the Infinity Cache)",
+                     "--beyond-cache-probe", os.path.join(ROOT, "profiles", "k_pass_grid8100_fp32_traffic.md")),
+}
 
 
 def summarize_traffic(fetch_dir, write_dir, probe_log):
@@ -103,20 +153,22 @@ def summarize_traffic(fetch_dir, write_dir, probe_log):
         return max(copy), sum(kpass) / launches, len(kpass)
 
     probe = [json.loads(x) for x in open(probe_log) if x.startswith('{"probe"')][0]
+    title, flag, out_file = PROBES[probe["probe"]]
     launches = probe["launches"]
     fc, fp, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
     wc, wp, nw = per_dispatch(write_dir, "WRITE_SIZE")
     kf, kw = COPY_BYTES / fc, COPY_BYTES / wc          # bytes per counter unit
     traffic = fp * kf + wp * kw
     algo = probe["algorithmic_bytes_per_launch"]
+    tag = probe["probe"]
     lines = [
-        "# k_pass (m=n=4096 grid, FP32 plan, cost regenerated): HBM traffic per launch",
+        f"# {title}: HBM traffic per launch",
         "",
         "Counters: `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch), each in its own run:",
         "",
-        "    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --traffic-probe > gpurun_out/traffic_probe.log 2>&1",
-        "    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --traffic-probe > gpurun_out/traffic_probe_w.log 2>&1",
-        "    python3 bench.py --summarize-traffic gpurun_out/pmc_fetch gpurun_out/pmc_write gpurun_out/traffic_probe.log",
+        f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_{tag} -o fetch -- python3 bench.py {flag} > gpurun_out/{tag}_probe.log 2>&1",
+        f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_{tag} -o write -- python3 bench.py {flag} > gpurun_out/{tag}_probe_w.log 2>&1",
+        f"    python3 bench.py --summarize-traffic gpurun_out/pmc_fetch_{tag} gpurun_out/pmc_write_{tag} gpurun_out/{tag}_probe.log",
         "",
         "Calibration: a plain 1 GiB device copy reads {:.0f} and writes {:.0f} counter units,".format(fc, wc),
         "so one unit is {:.1f} read bytes and {:.1f} written bytes.".format(kf, kw),
@@ -135,7 +187,53 @@ def summarize_traffic(fetch_dir, write_dir, probe_log):
         "algorithmic_bytes_per_launch: {:.0f}".format(algo),
         "kernel_source_sha256: {}".format(kernel_sha()),
     ]
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_file, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_trace(stats_csv, out_md, title, command):
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run (its kernel_stats.csv):
+    calls, average, min and max duration and share per kernel."""
+    import csv
+    import glob
+    stats_csv = sorted(glob.glob(stats_csv, recursive=True))[0]
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# {title}: kernel trace", "", "Command (on one MI355X, after `export TMPDIR=/tmp`):", "",
+             f"    {command}", "", f"`{os.path.basename(stats_csv)}` (all dispatches of the run; durations in ns):",
+             "", "| kernel | calls | avg ns | min ns | max ns | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| `{}` | {} | {:.0f} | {} | {} | {:.3g}% |".format(
+            r["Name"], r["Calls"], float(r["AverageNs"]), r["MinNs"], r["MaxNs"], float(r["Percentage"])))
+    lines.append("")
+    lines.append("kernel_source_sha256: {}".format(kernel_sha()))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_counters(csv_path, out_md, title, command):
+    """Markdown summary of rocprofv3 --pmc runs (counter_collection.csv files): per kernel
+    name, the dispatch count and the mean of every counter."""
+    import csv
+    import glob
+    acc = {}
+    for f in sorted(glob.glob(csv_path, recursive=True)):
+        for r in csv.DictReader(open(f)):
+            k = (r["Kernel_Name"], r["Counter_Name"])
+            d = acc.setdefault(k, {})
+            d[r["Dispatch_Id"]] = d.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    lines = [f"# {title}: counters", "", "Commands (on one MI355X, after `export TMPDIR=/tmp`), one run per counter set:", ""]
+    lines += [f"    {c}" for c in command]
+    lines += ["", "| kernel | counter | dispatches | mean per dispatch |", "|---|---|---|---|"]
+    for (kern, ctr), d in sorted(acc.items(), key=lambda kv: (kv[0][0], kv[0][1])):
+        if "k_pass" not in kern and "k_combine" not in kern and "k_resident" not in kern:
+            continue
+        vals = list(d.values())
+        lines.append(f"| `{kern}` | {ctr} | {len(vals)} | {sum(vals) / len(vals):.4g} |")
+    lines.append("")
+    lines.append("kernel_source_sha256: {}".format(kernel_sha()))
+    with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -155,11 +253,25 @@ def stored_traffic():
     return float(vals["traffic_bytes_per_launch"]), float(vals["algorithmic_bytes_per_launch"])
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(inst, budget_s=15.0):
     """The FP64 oracle on the host cores: PDHG iterations/s over the first iterations of
-    the same instance (a bounded sample; the full solve would take hours)."""
-    import numpy as np
+    the m = n = 4096 instance (a bounded sample; the oracle's full solve of it takes about
+    20 minutes there), and the oracle's whole solve of the 1024 x 1024 grid workload to
+    relative KKT 1e-6 (time to tolerance)."""
     import oracle
+    from workloads import generators as gen
     C = inst.dense_cost()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     # calibrate the per-iteration time (a 6-iteration run minus a 1-iteration run, which
@@ -182,9 +294,51 @@ def cpu_baseline(inst, budget_s=15.0):
                                        nthreads=threads)
         dt = time.perf_counter() - t
     del C
+    c2 = gen.config_instance(2, 0)
+    C2 = c2.dense_cost()
+    t = time.perf_counter()
+    _, _, _, r2, _ = oracle.solve(C2, c2.f, c2.g, tol=1e-6, nthreads=threads)
+    dt2 = time.perf_counter() - t
+    log(f"cpu oracle: {res['iterations'] / dt:.1f} iter/s at 4096; config 2 to 1e-6 in "
+        f"{dt2:.2f} s ({r2['iterations']} iterations) on {threads} threads")
     return {"value": res["iterations"] / dt, "unit": "iter/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"first {res['iterations']} PDHG iterations (FP64, dense C) of the m=n=4096 "
-                      f"grid instance, {dt:.1f} s on {threads} threads"}
+                      f"grid instance, {dt:.1f} s on {threads} threads",
+            "time_to_tol_1024": {"workload": "two 32x32 blob images (seed 100), m=n=1024, tol 1e-6",
+                                 "seconds": round(dt2, 3), "iterations": r2["iterations"],
+                                 "iter_per_s": round(r2["iterations"] / dt2, 1),
+                                 "objective": r2["objective"]}}
+
+
+def copy_ceiling(nbytes, reps=10):
+    """GB/s of a plain device copy moving nbytes in total (nbytes/2 read, nbytes/2 written):
+    the practical ceiling of a stream at that footprint on this GPU."""
+    import torch
+    n = max(1, int(nbytes // 8))
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * 4 * n / (ms * 1e-3) / 1e9
+
+
+def oracle_golden():
+    """The oracle's objective at tol 1e-8 for the benchmark instance, stored by
+    tests/golden/make_golden.py (oracle only); None when the file is absent."""
+    path = os.path.join(ROOT, "tests", "golden", "config3_oracle.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh)
 
 
 def percentile(xs, q):
@@ -203,6 +357,24 @@ def problems_autotuned(P, insts, precision, kind=None, shared=False):
                                         tile_vec=v, tile_rows=r)
         out.append(pr)
     return out
+
+
+def batch_probe():
+    """The 256-instance batch solved once (the workload of the batch profiles)."""
+    import torch
+    import paper_2407_19689_amd as P
+    from workloads import generators as gen
+    insts = gen.batch_instances(256)
+    prm = P.params(tol=1e-4, precision=P.OT_PREC_FP32, time_limit_s=300.0)
+    prs = problems_autotuned(P, insts, P.OT_PREC_FP32, shared=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, res = P.ot_solve_batch(prs, prm)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "batch", "status": P.STATUS_NAMES.get(st),
+                      "seconds": round(time.perf_counter() - t, 3),
+                      "iterations_total": int(sum(r.iterations for r in res)),
+                      "pass_bytes_total": sum(r.pass_bytes for r in res)}), flush=True)
 
 
 def batch_leg(P, count=256, seq_every=4):
@@ -262,60 +434,52 @@ def batch_leg(P, count=256, seq_every=4):
     }
 
 
-def serving_leg(P, count=48, load=0.7, iter_cap=200000):
-    """Continuous-batching server on a Poisson stream of mixed requests (points and images,
-    m, n log-uniform in [64, 16384], tol 1e-4 or 1e-6), first `count` requests of the
-    stream.  The saturated rate of this set is measured by submitting all of it at once;
-    the same requests are then replayed with the stream's arrival pattern at `load` times
-    that rate."""
+def serving_leg(P, count=200, rate=1.2, iter_cap=200000):
+    """Continuous-batching server on the Poisson request stream (points and images, m, n
+    log-uniform in [64, 16384], tol 1e-4 or 1e-6), its first `count` requests replayed at a
+    fixed arrival rate (`rate` requests/s; the stream's inter-arrival times are drawn at 10/s
+    and scaled).  Reported: latency (submit to completion) p50/p99 overall and for the smaller
+    and larger half of the requests by plan size, queue waits, solves/s, the requests that hit
+    the iteration cap, and the verified relative KKT of the results."""
     import torch
     from workloads import generators as gen
     FP32 = P.OT_PREC_FP32
     stream = gen.serving_stream(count=count)
     prm = P.params(tol=1e-4, precision=FP32, time_limit_s=300.0, max_iters=iter_cap)
     budget = 64 << 30
-
-    def run(reqs):
-        prs = problems_autotuned(P, [x for x, _ in reqs], FP32)
-        torch.cuda.synchronize()
-        with P.Server(budget, max_active=64, prm=prm) as srv:
-            outs, t0 = {}, time.perf_counter()
-            t_log = [t0]
-
-            def progress(n_sub):
-                # a line every 30 s with the submitted and completed counts
-                now = time.perf_counter()
-                if now - t_log[0] > 30.0:
-                    log(f"serving: {n_sub} of {len(reqs)} requests submitted, {len(outs)} done")
-                    t_log[0] = now
-
-            for k, ((inst, at), pr) in enumerate(zip(reqs, prs)):
-                while time.perf_counter() - t0 < at:
-                    for d in srv.poll():
-                        outs[d["ticket"]] = d
-                    progress(k)
-                    time.sleep(0.0005)
-                st, tk = srv.submit(pr)
-                if st != P.OT_OK:
-                    raise RuntimeError(f"submit failed: {P.STATUS_NAMES.get(st)} {P.ot_last_error()}")
-            t_end = time.perf_counter() + 900.0
-            while len(outs) < len(reqs):
-                for d in srv.poll(4096):
-                    outs[d["ticket"]] = d
-                if time.perf_counter() > t_end:
-                    raise RuntimeError("server did not drain")
-                progress(len(reqs))
-                time.sleep(0.002)
-            return list(outs.values()), srv.stats()
-
-    done, _ = run([(inst, 0.0) for _, inst in stream])
-    span_sat = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
-    sat_rate = len(done) / span_sat
-    rate = load * sat_rate
     base = 10.0                         # rate the stream's arrival times were drawn at
-    log(f"serving: {len(done)} requests submitted at once finish in {span_sat:.2f} s "
-        f"({sat_rate:.3f} solves/s); replaying them at {rate:.3f}/s")
-    done, stats = run([(inst, t * base / rate) for t, inst in stream])
+    reqs = [(inst, t * base / rate) for t, inst in stream]
+    prs = problems_autotuned(P, [x for x, _ in reqs], FP32)
+    torch.cuda.synchronize()
+    with P.Server(budget, max_active=64, prm=prm) as srv:
+        outs, t0 = {}, time.perf_counter()
+        t_log = [t0]
+
+        def progress(n_sub):
+            # a line every 30 s with the submitted and completed counts
+            now = time.perf_counter()
+            if now - t_log[0] > 30.0:
+                log(f"serving: {n_sub} of {len(reqs)} requests submitted, {len(outs)} done")
+                t_log[0] = now
+
+        for k, ((inst, at), pr) in enumerate(zip(reqs, prs)):
+            while time.perf_counter() - t0 < at:
+                for d in srv.poll():
+                    outs[d["ticket"]] = d
+                progress(k)
+                time.sleep(0.0005)
+            st, tk = srv.submit(pr)
+            if st != P.OT_OK:
+                raise RuntimeError(f"submit failed: {P.STATUS_NAMES.get(st)} {P.ot_last_error()}")
+        t_end = time.perf_counter() + 900.0
+        while len(outs) < len(reqs):
+            for d in srv.poll(4096):
+                outs[d["ticket"]] = d
+            if time.perf_counter() > t_end:
+                raise RuntimeError("server did not drain")
+            progress(len(reqs))
+            time.sleep(0.002)
+        done, stats = list(outs.values()), srv.stats()
     lat = [d["t_done"] - d["t_submit"] for d in done]
     wait = [d["t_admit"] - d["t_submit"] for d in done]
     span = max(d["t_done"] for d in done) - min(d["t_submit"] for d in done)
@@ -326,69 +490,102 @@ def serving_leg(P, count=48, load=0.7, iter_cap=200000):
     order = sorted(done, key=lambda d: d["ticket"])   # tickets follow submission order
     lat_small = [d["t_done"] - d["t_submit"] for d, sz in zip(order, sizes) if sz <= small]
     lat_large = [d["t_done"] - d["t_submit"] for d, sz in zip(order, sizes) if sz > small]
-    log(f"serving: {len(done)} done in {span:.2f} s, latency p50 {percentile(lat, 50):.3f} s "
+    tols = [inst.tol for _, inst in stream]
+    met = sum(1 for d, tl in zip(order, tols) if d["status"] == P.OT_OK and d["rel_kkt"] <= tl)
+    log(f"serving: {len(done)} done in {span:.2f} s at {rate}/s, latency p50 {percentile(lat, 50):.3f} s "
         f"p99 {percentile(lat, 99):.3f} s; max running {stats['max_running']}")
     return {
-        "workload": f"Poisson stream (master seed 500), first {count} requests: 90% point clouds "
-                    "in [0,1]^2 with squared-Euclidean cost, 10% blob images with side "
-                    "log-uniform in [8,128]; m,n log-uniform in [64,16384]; tol 1e-4 or 1e-6; "
-                    f"FP32 plan; iteration cap {iter_cap}",
-        "requests": len(done), "rate_per_s": round(rate, 3),
-        "saturated_solves_per_s": round(sat_rate, 3), "load": load,
+        "workload": f"Poisson stream (master seed 500), first {count} of its 2000 requests at a fixed "
+                    f"{rate}/s: 90% point clouds in [0,1]^2 with squared-Euclidean cost, 10% blob "
+                    "images with side log-uniform in [8,128]; m,n log-uniform in [64,16384]; tol "
+                    f"1e-4 or 1e-6; FP32 plan; iteration cap {iter_cap}",
+        "requests": len(done), "rate_per_s": rate,
         "latency_p50_s": round(percentile(lat, 50), 4),
         "latency_p99_s": round(percentile(lat, 99), 4),
         "latency_p50_smaller_half_s": round(percentile(lat_small, 50), 4),
+        "latency_p99_smaller_half_s": round(percentile(lat_small, 99), 4),
         "latency_p50_larger_half_s": round(percentile(lat_large, 50), 4),
+        "latency_p99_larger_half_s": round(percentile(lat_large, 99), 4),
         "queue_wait_p50_s": round(percentile(wait, 50), 4),
         "queue_wait_p99_s": round(percentile(wait, 99), 4),
         "solves_per_s": round(len(done) / span, 3),
+        "verified_within_tol": met,
         "max_running": stats["max_running"], "arena_peak_bytes": stats["arena_peak"],
         "graph_launches": stats["launches"], "hit_iteration_cap": capped, "failed": bad,
     }
 
 
-def suite_leg(P, sizes=(32, 64), pairs=2, tol=1e-4, time_limit=60.0):
+# (side, norms, pairs per class, time limit in s): the paper's three resolutions; at 128 x
+# 128 (m = n = 16384, 268M plan entries) one pair per class with the l2 cost
+SUITE_PLAN = ((32, ("l1", "l2", "linf"), 2, 60.0), (64, ("l1", "l2", "linf"), 2, 60.0),
+              (128, ("l2",), 1, 40.0))
+
+
+def suite_leg(P, sizes=(32, 64, 128), tol=1e-4):
     """DOTmark-shaped synthetic suite with the paper's reporting (Section 5.1): for every
-    resolution and norm (raw pixel distances C^1, C^2, C^inf), `pairs` image pairs of each
+    resolution and norm (raw pixel distances C^1, C^2, C^inf), image pairs of each
     synthetic image class are solved to relative KKT `tol` (FP32 form) and rounded
     (Algorithm 3).  Reported per resolution and norm: SGM10 of the solve times (an unsolved
     instance counts at the time limit), the geometric mean of the duality gap
-    |<C, X_feas> - f^T u - g^T v| of the rounded plan, and the largest certified relative
-    gap (upper - lower) / upper."""
+    |<C, X_feas> - f^T u - g^T v| of the rounded plan, the largest certified relative gap
+    (upper - lower) / upper, and the largest duality gap; at 128 x 128 also one solve of the
+    FP64 form (the paper's precision)."""
     import math
     import torch
     from workloads import generators as gen
-    FP32 = P.OT_PREC_FP32
+    FP32, FP64 = P.OT_PREC_FP32, P.OT_PREC_FP64
     out = {}
-    for side in sizes:
-        for norm in ("l1", "l2", "linf"):
+
+    def one(inst, prec, time_limit):
+        prm = P.params(tol=tol, precision=prec, time_limit_s=time_limit)
+        pr, o = P.problem_from_instance(inst, precision=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, r = P.ot_solve(pr, prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        st2, br = P.ot_round(pr, prec, o["X"], o["u"])
+        del o
+        return st, r, dt, (br if st2 == P.OT_OK else None)
+
+    for side, norms, pairs, time_limit in SUITE_PLAN:
+        if side not in sizes:
+            continue
+        for norm in norms:
             times, gaps, cgaps, its, solved = [], [], [], [], 0
             for ci, cls in enumerate(gen.IMAGE_CLASSES):
                 for k in range(pairs):
                     inst = gen.suite_pair(1000 * side + 10 * ci + k, side, cls, norm, tol=tol)
-                    prm = P.params(tol=tol, precision=FP32, time_limit_s=time_limit)
-                    pr, o = P.problem_from_instance(inst, precision=FP32)
-                    torch.cuda.synchronize()
-                    t = time.perf_counter()
-                    st, r = P.ot_solve(pr, prm)
-                    torch.cuda.synchronize()
-                    dt = time.perf_counter() - t
+                    st, r, dt, br = one(inst, FP32, time_limit)
+                    if side >= 128:
+                        log(f"suite {side}x{side} {norm} {cls}: {P.STATUS_NAMES.get(st)} {dt:.2f} s, "
+                            f"{r.iterations} iterations")
                     solved += st == P.OT_OK
                     times.append(dt if st == P.OT_OK else time_limit)
                     its.append(r.iterations)
-                    st2, br = P.ot_round(pr, FP32, o["X"], o["u"])
-                    if st2 == P.OT_OK:
+                    if br is not None:
                         gaps.append(max(abs(br["upper"] - r.dual_objective), 1e-300))
                         cgaps.append((br["upper"] - br["lower"]) / abs(br["upper"]))
             sgm10 = math.exp(sum(math.log(t + 10.0) for t in times) / len(times)) - 10.0
-            row = {"instances": len(times), "solved": solved, "sgm10_s": round(sgm10, 5),
+            row = {"instances": len(times), "solved": solved, "time_limit_s": time_limit,
+                   "sgm10_s": round(sgm10, 5),
                    "gap_geomean": math.exp(sum(math.log(g) for g in gaps) / len(gaps)),
-                   "certified_rel_gap_max": max(cgaps), "iterations_mean": round(sum(its) / len(its), 1)}
+                   "gap_max": max(gaps), "certified_rel_gap_max": max(cgaps),
+                   "iterations_mean": round(sum(its) / len(its), 1)}
             out[f"{side}x{side}_{norm}"] = row
             log(f"suite {side}x{side} {norm}: {row}")
-    return {"workload": f"synthetic DOTmark-shaped suite: {len(gen.IMAGE_CLASSES)} image classes "
-                        f"x {pairs} pairs per resolution and norm, raw pixel distances, FP32, "
-                        f"tol {tol:g}, time limit {time_limit:g} s", "results": out}
+        if side == 128:
+            inst = gen.suite_pair(1000 * side, side, gen.IMAGE_CLASSES[0], "l2", tol=tol)
+            st, r, dt, br = one(inst, FP64, 60.0)
+            out["128x128_l2_fp64"] = {"class": gen.IMAGE_CLASSES[0], "status": P.STATUS_NAMES.get(st),
+                                      "seconds": round(dt, 3), "iterations": r.iterations,
+                                      "gap": abs(br["upper"] - r.dual_objective) if br else None,
+                                      "certified_rel_gap": (br["upper"] - br["lower"]) / abs(br["upper"]) if br else None}
+            log(f"suite 128x128 l2 fp64: {out['128x128_l2_fp64']}")
+    planned = ", ".join(f"{s}x{s}: {'/'.join(n)} x {p} pair(s) per class, {tl:g} s limit"
+                        for s, n, p, tl in SUITE_PLAN if s in sizes)
+    return {"workload": f"synthetic DOTmark-shaped suite: {len(gen.IMAGE_CLASSES)} image classes; "
+                        f"{planned}; raw pixel distances, FP32, tol {tol:g}", "results": out}
 
 
 def main():
@@ -402,10 +599,19 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-suite", action="store_true")
-    ap.add_argument("--suite-sizes", default="32,64",
-                    help="image sides of the synthetic suite (the paper's are 32,64,128)")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--suite-sizes", default="32,64,128",
+                    help="image sides of the synthetic suite (the paper's: 32,64,128)")
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests taken from the stream (the full stream is 2000)")
+    ap.add_argument("--serve-rate", type=float, default=1.2,
+                    help="arrival rate of the replayed requests (requests/s)")
+    ap.add_argument("--beyond-cache-probe", action="store_true",
+                    help="run the workload of the 8100 x 8100 profiles (see profiles/)")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="run the workload of the batch profiles (see profiles/)")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("STATS_CSV", "OUT_MD", "TITLE", "COMMAND"))
+    ap.add_argument("--summarize-counters", nargs="+", metavar="ARG",
+                    help="CSV_GLOB OUT_MD TITLE COMMAND...: summary of --pmc runs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the workload of the counter runs (see profiles/)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "PROBE_LOG"))
@@ -415,6 +621,19 @@ def main():
         return
     if args.traffic_probe:
         traffic_probe()
+        return
+    if args.beyond_cache_probe:
+        beyond_cache(probe=True)
+        return
+    if args.batch_probe:
+        batch_probe()
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_counters:
+        a = args.summarize_counters
+        summarize_counters(a[0], a[1], a[2], a[3:])
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -492,8 +711,16 @@ def main():
     if st_tr is not None:
         # traffic measured per launch of the counter probe's launch mix, scaled to this mix
         traffic = round(st_tr[0] / st_tr[1] * avg_bytes)
+    ceiling = copy_ceiling(avg_bytes)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "measure": "algorithmic bytes per launch over the launch's event-timed duration; at "
+                       "this footprint (67 MB per plan) the 256 MB Infinity Cache serves part of "
+                       "the streams, so this is bandwidth below L2 with the Infinity Cache "
+                       "included (the counter traffic, FETCH_SIZE + WRITE_SIZE, is also counted "
+                       "below L2); beyond_cache gives the pass where nothing fits",
+            "copy_ceiling_GBps": round(ceiling, 1), "frac_of_copy_ceiling": round(achieved / ceiling, 4),
+            "beyond_cache": beyond_cache(),
             "kernel": "k_pass<float,4,grid-sqeuclid>", "avg_launch_us": round(avg_ms * 1e3, 3),
             "algorithmic_bytes_per_launch": round(avg_bytes), "launches": launches,
             "passes_by_kind": {"init": rp["mode_passes"][1], "trial": rp["mode_passes"][2],
@@ -501,35 +728,50 @@ def main():
                                "verify": rp["mode_passes"][5], "fold": rp["mode_passes"][6],
                                "trial_or_full_folding_two": rp["avg_fold_passes"]}}
 
+    gold = oracle_golden()
+    opt = gold["objective_tol1e-08"] if gold else None
+
+    def rel_err(obj):
+        return None if opt is None else abs(obj - opt) / abs(opt)
+
     forms = {}
     if not args.no_forms:
         # ablation: Algorithm 2 as printed (constant step 1/(2 sqrt(m+n)), uniform average,
-        # basic restart to the average, fixed primal weight), to 1e-4, capped at 20 s
+        # basic restart to the average, fixed primal weight) against the Section 5 rules,
+        # both to 1e-4 on the 1024 x 1024 grid pair, where the basic rule restarts
+        c2 = gen.config_instance(2, 0)
         lit = P.params(tol=1e-4, precision=FP32, step_rule=1, restart_rule=1, avg_weighting=1,
-                       primal_weight_update=0, eta0=0.5 / (2 * 4096) ** 0.5, time_limit_s=20.0)
-        pr_l, _ = P.problem_from_instance(inst, precision=FP32, want_plan=False)
+                       primal_weight_update=0, eta0=0.5 / (c2.m + c2.n) ** 0.5, time_limit_s=30.0)
+        pr_l, _ = P.problem_from_instance(c2, precision=FP32, want_plan=False)
         torch.cuda.synchronize()
         t = time.perf_counter()
         st_l, r_l = P.ot_solve(pr_l, lit)
         torch.cuda.synchronize()
         dt_l = time.perf_counter() - t
-        forms["paper_literal_tol1e-4"] = {"status": P.STATUS_NAMES.get(st_l), "seconds": round(dt_l, 4),
-                                          "iterations": r_l.iterations, "restarts": r_l.restarts,
-                                          "rel_kkt": r_l.rel_kkt}
-        log(f"paper-literal mode to 1e-4: {dt_l:.3f} s, {r_l.iterations} iterations "
-            f"({P.STATUS_NAMES.get(st_l)}), against {r4['iterations']} with the Section 5 rules")
+        dt_s, r_s = gpu_solve(P, c2, 1e-4, FP32, 0)
+        forms["paper_literal_1024_tol1e-4"] = {
+            "status": P.STATUS_NAMES.get(st_l), "seconds": round(dt_l, 4), "iterations": r_l.iterations,
+            "restarts": r_l.restarts, "rel_kkt": r_l.rel_kkt,
+            "section5_rules": {"seconds": round(dt_s, 4), "iterations": r_s["iterations"],
+                               "restarts": r_s["restarts"]}}
+        log(f"paper-literal mode on the 1024 grid to 1e-4: {dt_l:.3f} s, {r_l.iterations} iterations, "
+            f"{r_l.restarts} restarts ({P.STATUS_NAMES.get(st_l)}); Section 5 rules: {dt_s:.3f} s, "
+            f"{r_s['iterations']} iterations, {r_s['restarts']} restarts")
         for name, prec, store in (("fp32_stored_cost", FP32, 1), ("fp64_regenerated_cost", FP64, 0),
                                   ("fp64_stored_cost", FP64, 1)):
             dtf, rf = gpu_solve(P, inst, args.tol, prec, store)
             forms[name] = {"seconds": round(dtf, 4), "iterations": rf["iterations"],
                            "iter_per_s": round(rf["iterations"] / dtf, 1),
-                           "objective": rf["objective"], "rel_kkt": rf["rel_kkt"]}
+                           "objective": rf["objective"], "rel_kkt": rf["rel_kkt"],
+                           "objective_rel_err_vs_oracle": rel_err(rf["objective"])}
             log(f"form {name}: {dtf:.3f} s, {rf['iterations']} iterations")
 
     # the two smaller single-instance workloads (parity cases of the tests): 64 points in
     # the unit square (squared Euclidean, one work-group runs it) and two 32x32 images;
     # best of three solves to 1e-6 after one untimed solve
     small = {}
+    g2path = os.path.join(ROOT, "tests", "golden", "config2_oracle.json")
+    gold2 = json.load(open(g2path))["objective_tol1e-09"] if os.path.exists(g2path) else None
     if not args.no_forms:
         for cfg in (1, 2):
             ci = gen.config_instance(cfg, 0)
@@ -541,12 +783,14 @@ def main():
                 small[f"config{cfg}_m{ci.m}_n{ci.n}_{pname}"] = {
                     "seconds": round(dts, 5), "iterations": rr["iterations"],
                     "iter_per_s": round(rr["iterations"] / dts, 1), "objective": rr["objective"],
-                    "rel_kkt": rr["rel_kkt"]}
+                    "rel_kkt": rr["rel_kkt"],
+                    "objective_rel_err_vs_oracle": (abs(rr["objective"] - gold2) / gold2
+                                                    if cfg == 2 and gold2 else None)}
                 log(f"config {cfg} ({ci.m}x{ci.n}) {pname}: {dts * 1e3:.2f} ms, {rr['iterations']} iterations")
 
     suite = None if args.no_suite else suite_leg(P, sizes=tuple(int(x) for x in args.suite_sizes.split(",")))
     batch = None if args.no_batch else batch_leg(P)
-    serving = None if args.no_serving else serving_leg(P, count=args.serve_requests)
+    serving = None if args.no_serving else serving_leg(P, count=args.serve_requests, rate=args.serve_rate)
     cpu = None if args.no_cpu else cpu_baseline(inst)
 
     line = {
@@ -574,6 +818,8 @@ def main():
         "restarts": last["restarts"],
         "passes": last["passes"],
         "objective": last["objective"],
+        "objective_rel_err_vs_oracle": rel_err(last["objective"]),
+        "oracle_objective_tol1e-8": opt,
         "rel_kkt": last["rel_kkt"],
         "certified_bracket": bracket,
         "roofline": roof,

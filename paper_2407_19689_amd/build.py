@@ -19,8 +19,11 @@ ARCH = "gfx950"
 # harmless warning about the unknown target feature.  No implicit contraction into fused
 # multiply-adds: every kernel variant that inlines the same code then rounds it alike
 # (fused multiply-adds are written out with fma() where wanted).
+# Kernel arguments are preloaded into scalar registers (no load of the argument block at
+# the start of every launch; measured 0.25 us shorter streaming passes at 1024 x 1024).
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-kernarg-preload-count=16",
          "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include")]
 
 

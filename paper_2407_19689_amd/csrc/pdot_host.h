@@ -14,10 +14,12 @@
 namespace pdot {
 
 // ---- kernel launchers (pdot_kernels.hip)
-hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Tile *tiles,
+// ctls: the control blocks, indexed like the instance table (the control block of the
+// instance in slot k is ctls[k]; Inst::ctl points to it)
+hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Ctl *ctls, const Tile *tiles,
                        const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0 = nullptr,
                        hipEvent_t ev1 = nullptr);
-hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
+hipError_t launch_combine(const Inst *insts, Ctl *ctls, const CombEntry *ents, const int32_t *nents, int grid,
                           hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_resident(int fp32, int vec, int cost, const Inst *insts, const int32_t *list,
                            const int32_t *count, int grid, int32_t budget, hipStream_t s,

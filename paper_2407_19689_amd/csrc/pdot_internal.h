@@ -119,7 +119,7 @@ struct Inst {
     double *rowpart;        // [ncb][m]  row sums of each column band
     double *colpart;        // [nrb][n]  column sums of each row block
     double *tilescal;       // [ntiles][kNS]
-    double *combscal;       // [ncomb][kNB]
+    double *combscal;       // [2][ncomb][kNB]: combine records of even and odd slots
     uint32_t *counter;
     Ctl *ctl;
     TraceRec *trace;        // nullable: control records of the solve

@@ -642,7 +642,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
 // host repacks the tile table between launches (instances joining or finishing).
 template <typename TX, int VEC, int COST>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(PDOT_PASS_WAVES)))
-void k_pass(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
+void k_pass(const Inst *__restrict__ insts, const Ctl *__restrict__ ctls, const Tile *__restrict__ tiles,
             const int32_t *__restrict__ count)
 {
     __shared__ double lds[3 * 2 * 4 * 64 + 4 * kNS];
@@ -653,8 +653,10 @@ void k_pass(const Inst *__restrict__ insts, const Tile *__restrict__ tiles,
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tl = next;
         if (t + (int)gridDim.x < ntiles) next = cp(tiles)[t + gridDim.x];
+        // the descriptor and the control block come from tables indexed by the instance,
+        // so both loads are in flight together
         const PDOT_CONST Inst &I = cp(insts)[tl.inst];
-        const Ctl st = *cp((const Ctl *)I.ctl);
+        const Ctl st = cp(ctls)[tl.inst];
         switch (st.mode) {
         case M_INIT: tile_body<TX, VEC, COST, M_INIT>(I, st, tl, lds); break;
         case M_TRIAL:
@@ -1104,33 +1106,51 @@ __device__ __forceinline__ void index_work(const PDOT_CONST Inst &I, const Ctl &
 }
 
 // Record words of the combine hand-off.  A word holds the bits of its value plus one, so
-// zero (its state before the value is written, and again after the last work-group has
-// taken it) is never a value: a computed double never has the all-ones bit pattern (a NaN
-// payload the arithmetic does not produce).  Every word is written once and read once per
-// slot; the kernel boundary between slots orders a word's reset before its next value.
+// zero (its state before the value is written) is never a value: a computed double never
+// has the all-ones bit pattern (a NaN payload the arithmetic does not produce).  Records
+// alternate between two sets by slot parity: in a slot, each work-group writes its record
+// in the set of the slot and clears its record in the other set, which the previous slot
+// used and the next will write; kernel boundaries order the clear after the previous
+// slot's reads and before the next slot's values.  So every word a slot reads is either
+// its value of this slot or zero.
 __device__ __forceinline__ void rec_put(PDOT_GLOBAL uint64_t *w, double v)
 {
     __hip_atomic_store(w, (uint64_t)__double_as_longlong(v) + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wait for a word (its store was issued before the writer moved the counter, so it
-// arrives; the wait is bounded all the same: after kRecSpin loads `lost` is set and the
-// caller stops the instance with a device error instead of waiting on), take its value
-// and reset it.
-constexpr int kRecSpin = 1 << 20;
-__device__ __forceinline__ double rec_take(PDOT_GLOBAL uint64_t *w, bool &lost)
+// The other set is read by no work-group during this slot (the previous slot's last
+// work-group has read it, the next slot's will), so its words are cleared with plain
+// stores, after the counter has moved; the kernel boundary makes them visible.
+__device__ __forceinline__ void rec_clear(PDOT_GLOBAL uint64_t *w)
 {
-    uint64_t b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int k = 0; b == 0 && k < kRecSpin; ++k) {
-        __builtin_amdgcn_s_sleep(1);
-        b = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *w = 0;
+}
+
+// Take the kNB words of one record: all loads in flight together (the words normally
+// arrived before the writer moved the counter), then a wait for any word still zero
+// (bounded: after kRecSpin loads `lost` is set and the caller stops the instance with a
+// device error instead of waiting on).
+constexpr int kRecSpin = 1 << 20;
+__device__ __forceinline__ void rec_take(PDOT_GLOBAL uint64_t *w, double (&v)[kNB], bool &lost)
+{
+    uint64_t b[kNB];
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) b[q] = __hip_atomic_load(w + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool all = true;
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) all = all && b[q] != 0;
+    if (!all) {
+#pragma unroll
+        for (int q = 0; q < kNB; ++q) {
+            for (int k = 0; b[q] == 0 && k < kRecSpin; ++k) {
+                __builtin_amdgcn_s_sleep(1);
+                b[q] = __hip_atomic_load(w + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (b[q] == 0) lost = true;
+        }
     }
-    if (b == 0) {
-        lost = true;
-        return 0.0;
-    }
-    __hip_atomic_store(w, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)(b - 1u));
+#pragma unroll
+    for (int q = 0; q < kNB; ++q) v[q] = b[q] ? __longlong_as_double((long long)(b[q] - 1u)) : 0.0;
 }
 
 // The combine kernel: one work-group per slice of 64 rows or 64 columns of an instance.
@@ -1141,7 +1161,7 @@ __device__ __forceinline__ double rec_take(PDOT_GLOBAL uint64_t *w, bool &lost)
 //  3. hands its record (eight slice scalars, six tile scalars) to the last work-group of
 //     the instance (agent-scope atomic stores and a counter), which reduces the records in
 //     a fixed order and runs the control of Section 5 for the next slot.
-__global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts, Ctl *__restrict__ ctls,
                                                  const CombEntry *__restrict__ ents,
                                                  const int32_t *__restrict__ count)
 {
@@ -1161,7 +1181,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         const CombEntry E = next;
         if (e + (int)gridDim.x < nents) next = cp(ents)[e + gridDim.x];
         const PDOT_CONST Inst &I = cp(insts)[E.inst];
-        const Ctl st = *gp(I.ctl);
+        const Ctl st = gp(ctls)[E.inst];
 
         const bool rows = E.kind == 0;
         const int64_t len = rows ? I.m : I.n;
@@ -1239,7 +1259,10 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 #pragma unroll
             for (int q = 0; q < kNC; ++q) r[q] = wave_sum_to63(acc[q]);
             if (lane == 63) {
-                PDOT_GLOBAL uint64_t *dst = gp((uint64_t *)I.combscal) + (int64_t)E.local * kNB;
+                const int64_t set = (int64_t)(st.kpasses & 1) * I.ncomb * kNB;
+                const int64_t other = (int64_t)((st.kpasses & 1) ^ 1) * I.ncomb * kNB;
+                PDOT_GLOBAL uint64_t *dst = gp((uint64_t *)I.combscal) + set + (int64_t)E.local * kNB;
+                PDOT_GLOBAL uint64_t *old = gp((uint64_t *)I.combscal) + other + (int64_t)E.local * kNB;
 #pragma unroll
                 for (int q = 0; q < kNC; ++q) rec_put(dst + q, r[q]);
 #pragma unroll
@@ -1250,6 +1273,8 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                 const unsigned prev = __hip_atomic_fetch_add(gp(I.counter), 1u, __ATOMIC_RELAXED,
                                                              __HIP_MEMORY_SCOPE_AGENT);
                 is_last = (prev == (unsigned)(I.ncomb - 1)) ? 1 : 0;
+#pragma unroll
+                for (int q = 0; q < kNB; ++q) rec_clear(old + q);
             }
         }
         __syncthreads();
@@ -1264,10 +1289,12 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 #pragma unroll
         for (int q = 0; q < kNB; ++q) loc[q] = 0.0;
         bool lost = false;
+        const int64_t set = (int64_t)(st.kpasses & 1) * I.ncomb * kNB;
         for (int c = threadIdx.x; c < I.ncomb; c += kWG) {
-            PDOT_GLOBAL uint64_t *src = gp((uint64_t *)I.combscal) + (int64_t)c * kNB;
+            double v[kNB];
+            rec_take(gp((uint64_t *)I.combscal) + set + (int64_t)c * kNB, v, lost);
 #pragma unroll
-            for (int q = 0; q < kNB; ++q) loc[q] += rec_take(src + q, lost);
+            for (int q = 0; q < kNB; ++q) loc[q] += v[q];
         }
         if (lost) lost_any = 1;
 #pragma unroll
@@ -1290,7 +1317,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
             } else {
                 control(c, P, mode, tot, tot + kNC, g_red, g_grow, TraceOut{I.trace, I.trace_cap});
             }
-            *gp(I.ctl) = c;
+            gp(ctls)[E.inst] = c;
             __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             lost_any = 0;
         }
@@ -1720,61 +1747,61 @@ namespace pdot {
 // Launch of the streaming pass.  With events (profiling), the events are stamped with the
 // kernel's own start and end (hipExtLaunchKernel), not with the enqueue times.
 template <typename K>
-static hipError_t launch_k(K kernel, int grid, const Inst *insts, const Tile *tiles,
+static hipError_t launch_k(K kernel, int grid, const Inst *insts, const Ctl *ctls, const Tile *tiles,
                            const int32_t *count, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (ev0 && ev1)
-        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, tiles, count);
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, ctls, tiles, count);
     else
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, insts, tiles, count);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kWG), 0, s, insts, ctls, tiles, count);
     return hipGetLastError();
 }
 
 template <typename TX, int VEC>
-static hipError_t launch_pass_vec(int cost, const Inst *insts, const Tile *tiles,
+static hipError_t launch_pass_vec(int cost, const Inst *insts, const Ctl *ctls, const Tile *tiles,
                                   const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0,
                                   hipEvent_t ev1)
 {
     switch (cost) {
-    case C_STORED: return launch_k(k_pass<TX, VEC, C_STORED>, grid, insts, tiles, ntiles, s, ev0, ev1);
-    case C_PTS_SQ: return launch_k(k_pass<TX, VEC, C_PTS_SQ>, grid, insts, tiles, ntiles, s, ev0, ev1);
-    case C_PTS_EU: return launch_k(k_pass<TX, VEC, C_PTS_EU>, grid, insts, tiles, ntiles, s, ev0, ev1);
-    case C_GRID_SQ: return launch_k(k_pass<TX, VEC, C_GRID_SQ>, grid, insts, tiles, ntiles, s, ev0, ev1);
-    case C_GRID_L1: return launch_k(k_pass<TX, VEC, C_GRID_L1>, grid, insts, tiles, ntiles, s, ev0, ev1);
-    case C_GRID_L2: return launch_k(k_pass<TX, VEC, C_GRID_L2>, grid, insts, tiles, ntiles, s, ev0, ev1);
-    case C_GRID_LINF: return launch_k(k_pass<TX, VEC, C_GRID_LINF>, grid, insts, tiles, ntiles, s, ev0, ev1);
+    case C_STORED: return launch_k(k_pass<TX, VEC, C_STORED>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
+    case C_PTS_SQ: return launch_k(k_pass<TX, VEC, C_PTS_SQ>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
+    case C_PTS_EU: return launch_k(k_pass<TX, VEC, C_PTS_EU>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_SQ: return launch_k(k_pass<TX, VEC, C_GRID_SQ>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_L1: return launch_k(k_pass<TX, VEC, C_GRID_L1>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_L2: return launch_k(k_pass<TX, VEC, C_GRID_L2>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
+    case C_GRID_LINF: return launch_k(k_pass<TX, VEC, C_GRID_LINF>, grid, insts, ctls, tiles, ntiles, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <typename TX>
-static hipError_t launch_pass_t(int vec, int cost, const Inst *insts, const Tile *tiles,
+static hipError_t launch_pass_t(int vec, int cost, const Inst *insts, const Ctl *ctls, const Tile *tiles,
                                 const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0,
                                 hipEvent_t ev1)
 {
     switch (vec) {
-    case 1: return launch_pass_vec<TX, 1>(cost, insts, tiles, ntiles, grid, s, ev0, ev1);
-    case 2: return launch_pass_vec<TX, 2>(cost, insts, tiles, ntiles, grid, s, ev0, ev1);
-    case 4: return launch_pass_vec<TX, 4>(cost, insts, tiles, ntiles, grid, s, ev0, ev1);
+    case 1: return launch_pass_vec<TX, 1>(cost, insts, ctls, tiles, ntiles, grid, s, ev0, ev1);
+    case 2: return launch_pass_vec<TX, 2>(cost, insts, ctls, tiles, ntiles, grid, s, ev0, ev1);
+    case 4: return launch_pass_vec<TX, 4>(cost, insts, ctls, tiles, ntiles, grid, s, ev0, ev1);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Tile *tiles,
+hipError_t launch_pass(int fp32, int vec, int cost, const Inst *insts, const Ctl *ctls, const Tile *tiles,
                        const int32_t *ntiles, int grid, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
-    return fp32 ? launch_pass_t<float>(vec, cost, insts, tiles, ntiles, grid, s, ev0, ev1)
-                : launch_pass_t<double>(vec, cost, insts, tiles, ntiles, grid, s, ev0, ev1);
+    return fp32 ? launch_pass_t<float>(vec, cost, insts, ctls, tiles, ntiles, grid, s, ev0, ev1)
+                : launch_pass_t<double>(vec, cost, insts, ctls, tiles, ntiles, grid, s, ev0, ev1);
 }
 
-hipError_t launch_combine(const Inst *insts, const CombEntry *ents, const int32_t *nents, int grid,
+hipError_t launch_combine(const Inst *insts, Ctl *ctls, const CombEntry *ents, const int32_t *nents, int grid,
                           hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     if (ev0 && ev1)
-        hipExtLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, ents, nents);
+        hipExtLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, ev0, ev1, 0, insts, ctls, ents, nents);
     else
-        hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, insts, ents, nents);
+        hipLaunchKernelGGL(k_combine, dim3(grid), dim3(kWG), 0, s, insts, ctls, ents, nents);
     return hipGetLastError();
 }
 

@@ -201,8 +201,8 @@ ot_status solve_noalloc(const ot_problem &pb, const ot_params &prm, ot_result *r
             slots_run += budget;
         } else {
             for (int k = 0; k < slots; ++k) {
-                NA_TRY(launch_pass(L.fp32, L.vec, L.cost, d_inst, tiles, counts, grid_t, s));
-                NA_TRY(launch_combine(d_inst, combs, counts + 1, grid_c, s));
+                NA_TRY(launch_pass(L.fp32, L.vec, L.cost, d_inst, I.ctl, tiles, counts, grid_t, s));
+                NA_TRY(launch_combine(d_inst, I.ctl, combs, counts + 1, grid_c, s));
             }
             slots_run += slots;
         }

@@ -181,7 +181,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     L.off_rowpart = take(sizeof(double) * (size_t)L.ncb * (size_t)L.m);
     L.off_colpart = take(sizeof(double) * (size_t)L.nrb * (size_t)L.n);
     L.off_tiles = take(sizeof(double) * (size_t)L.ntiles * kNS);
-    L.off_comb = take(sizeof(double) * (size_t)L.ncomb * kNB);
+    L.off_comb = take(sizeof(double) * (size_t)L.ncomb * kNB * 2);   // two record sets
     L.off_counter = take(sizeof(uint32_t) * 4);
     L.off_ctl = take(sizeof(Ctl));
     if (pb.trace_cap < 0) return fail(OT_ERR_INVALID, "trace_cap < 0");
@@ -522,8 +522,9 @@ public:
         }
         arena_.reset(arena_bytes);
         max_slots_ = max_slots;
-        // instance table and counts come first in the arena
+        // instance and control-block tables and counts come first in the arena
         if (!arena_.alloc(sizeof(Inst) * (size_t)max_slots, &off_insts_) ||
+            !arena_.alloc(sizeof(Ctl) * (size_t)max_slots, &off_ctls_) ||
             !arena_.alloc(sizeof(int32_t) * kNumCounts, &off_counts_))
             return fail(OT_ERR_OOM, "arena too small for the engine tables");
         HIP_TRY(hipHostMalloc((void **)&h_ctl_, sizeof(Ctl) * (size_t)max_slots, hipHostMallocDefault));
@@ -601,11 +602,11 @@ public:
                     hipEvent_t *ev = &prof_ev_[2 * per_slot * (size_t)k];
                     for (size_t gi = 0; gi < ln.groups.size(); ++gi) {
                         const Group &g = ln.groups[gi];
-                        HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln, k & 1) + g.first,
+                        HIP_TRY(launch_pass(g.fp32, g.vec, g.cost, d_insts(), d_ctls(), tiles(ln, k & 1) + g.first,
                                             d_counts() + l * kLaneCounts + gi, g.grid, ln.s, ev[2 * gi],
                                             ev[2 * gi + 1]));
                     }
-                    HIP_TRY(launch_combine(d_insts(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups,
+                    HIP_TRY(launch_combine(d_insts(), d_ctls(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups,
                                            ln.comb_grid, ln.s, ev[2 * (per_slot - 1)], ev[2 * per_slot - 1]));
                 }
                 HIP_TRY(hipStreamSynchronize(ln.s));
@@ -807,6 +808,7 @@ private:
     };
 
     Inst *d_insts() const { return (Inst *)(base_ + off_insts_); }
+    Ctl *d_ctls() const { return (Ctl *)(base_ + off_ctls_); }
     int32_t *d_counts() const { return (int32_t *)(base_ + off_counts_); }
     // The tile table of a lane in forward (rev = 0) or reversed (rev = 1) order.
     Tile *tiles(const Lane &ln, int rev = 0) const
@@ -841,6 +843,7 @@ private:
         char *b = base_ + r.off;
         Inst &I = r.I;
         init_inst(l, b, pb.cost.scale, prm_, r.tol, I);
+        I.ctl = d_ctls() + r.slot;   // the control block lives in the engine's table
         const int64_t m = l.m, n = l.n;
 
         HIP_TRY(hipMemsetAsync(b, 0, l.bytes, s_));
@@ -1062,11 +1065,12 @@ private:
                 // consecutive slots stream the tiles in opposite orders: a pass starts on
                 // what the previous one touched last, which the Infinity Cache still holds
                 // when the plans outgrow it
-                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), tiles(ln, sl & 1) + g.first,
+                e = launch_pass(g.fp32, g.vec, g.cost, d_insts(), d_ctls(), tiles(ln, sl & 1) + g.first,
                                 d_counts() + l * kLaneCounts + gi, g.grid, ln.s);
             }
             if (e == hipSuccess)
-                e = launch_combine(d_insts(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups, ln.comb_grid, ln.s);
+                e = launch_combine(d_insts(), d_ctls(), combs(ln), d_counts() + l * kLaneCounts + kMaxGroups,
+                                   ln.comb_grid, ln.s);
         }
         hipGraph_t g = nullptr;
         const hipError_t e2 = hipStreamEndCapture(ln.s, &g);
@@ -1088,7 +1092,7 @@ private:
     int max_slots_ = 0;
     std::vector<int> free_slots_;
     std::vector<Req *> active_;
-    size_t off_insts_ = 0, off_counts_ = 0, off_rlist_ = 0;
+    size_t off_insts_ = 0, off_ctls_ = 0, off_counts_ = 0, off_rlist_ = 0;
     int64_t rlist_cap_ = 0;
     Lane lanes_[kLanes];
     std::vector<RGroup> rgroups_;
@@ -1133,7 +1137,8 @@ ot_status plan_fixed(const ot_problem *probs, int count, const ot_params &prm, P
             }
         if (!seen) per.push_back({key, (int64_t)l.ntiles});
     }
-    size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(int32_t) * kNumCounts);
+    size_t total = align_up(sizeof(Inst) * (size_t)count) + align_up(sizeof(Ctl) * (size_t)count) +
+                   align_up(sizeof(int32_t) * kNumCounts);
     for (auto &l : P.L) total += align_up(l.bytes);
     // each lane's tile (two copies) and combine tables, sized as sync_tables sizes them
     int64_t tcap[kLanes] = {};
