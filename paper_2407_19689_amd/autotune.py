@@ -1,6 +1,8 @@
 """Tile-shape autotuner for the streaming pass.
 
-For each cost kind and precision, representative instances on a grid of size buckets
+For each cost kind (Euclidean and squared-Euclidean point clouds; images under the
+squared-Euclidean, l1, l2 and l-infinity ground costs) and precision (FP32 and FP64
+plans), representative instances on a grid of size buckets
 (m, n = powers of two) are solved for a fixed number of iterations with every candidate
 tile shape (columns per lane VEC in {1, 2, 4}, rows per tile in {16, ..., 256}) in
 profiling mode; the shape with the smallest measured slot time (streaming pass plus
@@ -12,7 +14,8 @@ The tile shape only changes the order of the deterministic reductions, never the
 so every choice gives a valid solve; the batch and the server take the per-instance
 choice through `ot_problem.tile_vec / tile_rows`.
 
-Usage (on the GPU):  python -m paper_2407_19689_amd.autotune [--quick]
+Usage (on the GPU):
+    python -m paper_2407_19689_amd.autotune [--quick] [--kinds K1,K2] [--precisions 1,0]
 """
 import argparse
 import json
@@ -22,11 +25,12 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "autotune_gfx950.json")
-KINDS = ("points_euclid", "points_sqeuclid", "grid_sqeuclid")
+GRID_KINDS = ("grid_sqeuclid", "grid_l1", "grid_l2", "grid_linf")
+KINDS = ("points_euclid", "points_sqeuclid") + GRID_KINDS
 # size buckets (log2 m = log2 n range) per cost kind: Euclidean point clouds for batches of
 # 32..2048 points, squared-Euclidean clouds and square images for requests up to 16384
-EXPS = {"points_euclid": range(5, 12), "points_sqeuclid": range(6, 15),
-        "grid_sqeuclid": range(6, 15, 2)}
+EXPS = {"points_euclid": range(5, 12), "points_sqeuclid": range(6, 15)}
+EXPS.update({k: range(6, 15, 2) for k in GRID_KINDS})
 
 
 def bucket(m, n):
@@ -83,7 +87,7 @@ def _instance(kind, m, n, seed):
     if kind == "points_sqeuclid":
         return gen.points_sqeuclid(seed, m, n)
     side = int(round(math.sqrt(m)))
-    return gen.grid_pair(seed, side)
+    return gen.grid_pair(seed, side, kind=kind)
 
 
 def measure(inst, precision, vec, rows, iters):
@@ -101,12 +105,13 @@ def measure(inst, precision, vec, rows, iters):
 
 
 def tune(kinds=KINDS, precision=1, quick=False, iters=60, verbose=True, out=None):
-    cache = dict(load_cache())
+    # start from the output file when it exists (several calls add to one file)
+    cache = dict(json.load(open(out)) if out and os.path.exists(out) else load_cache())
     for kind in kinds:
-        exps = list(EXPS[kind])[::2] if quick and kind != "grid_sqeuclid" else EXPS[kind]
+        exps = list(EXPS[kind])[::2] if quick and kind not in GRID_KINDS else EXPS[kind]
         for em in exps:
             for en in exps:
-                if kind == "grid_sqeuclid" and em != en:
+                if kind in GRID_KINDS and em != en:
                     continue              # square images only: m = n = side^2
                 m, n = 2 ** em, 2 ** en
                 inst = _instance(kind, m, n, seed=em * 100 + en)
@@ -126,10 +131,10 @@ def tune(kinds=KINDS, precision=1, quick=False, iters=60, verbose=True, out=None
                 cache[_key(precision, kind, *bucket(m, n))] = {
                     "vec": best[1], "rows": best[2], "slot_ms": round(best[0], 5), "m": m, "n": n}
                 if verbose:
-                    print(f"{kind} m={m} n={n}: vec={best[1]} rows={best[2]} "
+                    print(f"p{precision} {kind} m={m} n={n}: vec={best[1]} rows={best[2]} "
                           f"slot {best[0] * 1e3:.1f} us", flush=True)
-    with open(out or CACHE, "w") as fh:
-        json.dump(cache, fh, indent=1, sort_keys=True)
+        with open(out or CACHE, "w") as fh:   # after every kind: a cut-off run keeps its results
+            json.dump(cache, fh, indent=1, sort_keys=True)
     return cache
 
 
@@ -137,12 +142,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true", help="fewer buckets and iterations")
     ap.add_argument("--kinds", default=",".join(KINDS))
+    ap.add_argument("--precisions", default="1,0", help="1: FP32 plan, 0: FP64 plan")
     ap.add_argument("--out", default=None, help="write the cache here instead of next to the module")
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
     t = time.time()
-    tune(kinds=args.kinds.split(","), quick=args.quick, iters=40 if args.quick else 60, out=args.out)
+    for prec in (int(p) for p in args.precisions.split(",")):
+        tune(kinds=args.kinds.split(","), precision=prec, quick=args.quick,
+             iters=40 if args.quick else 60, out=args.out)
     print(f"autotune done in {time.time() - t:.1f} s -> {args.out or CACHE}", flush=True)
 
 

@@ -824,18 +824,12 @@ __device__ __forceinline__ void step_decide(Ctl &c, const Prm &P, double dx2, do
 __device__ __forceinline__ void control(Ctl &c, const Prm &P, int mode, const double *cs, const double *ts,
                         double g_red, double g_grow, const TraceOut &to)
 {
-    // constant indices only: an array of the control block indexed at run time would put
-    // the whole block in scratch memory
+    // Constant indices only: an array of the control block indexed at run time goes to
+    // scratch memory, and its load-add-store would put a memory round trip on the slot's
+    // critical path (a switch over the modes is folded back into such an index).
     c.kpasses += 1;
-    switch (mode) {
-    case M_INIT: c.mcount[M_INIT] += 1; break;
-    case M_TRIAL: c.mcount[M_TRIAL] += 1; break;
-    case M_FULL: c.mcount[M_FULL] += 1; break;
-    case M_RESTART: c.mcount[M_RESTART] += 1; break;
-    case M_VERIFY: c.mcount[M_VERIFY] += 1; break;
-    case M_FOLD: c.mcount[M_FOLD] += 1; break;
-    default: break;
-    }
+#pragma unroll
+    for (int k = M_INIT; k < kModes; ++k) c.mcount[k] += mode == k ? 1 : 0;
     if ((mode == M_TRIAL || mode == M_FULL) && c.lag) c.fold2 += 1;
     if (mode == M_INIT) {
         c.norm_b = sqrt(cs[CS_AUX]);
@@ -1153,6 +1147,22 @@ __device__ __forceinline__ void rec_take(PDOT_GLOBAL uint64_t *w, double (&v)[kN
     for (int q = 0; q < kNB; ++q) v[q] = b[q] ? __longlong_as_double((long long)(b[q] - 1u)) : 0.0;
 }
 
+// The run parameters of an instance, with vector loads all in flight together.  Through
+// the scalar cache the control would fetch each field where it first uses it, one
+// dependent miss after another on the slot's critical path.
+static_assert(sizeof(Prm) % 8 == 0, "Prm is loaded in 8-byte words");
+__device__ __forceinline__ Prm prm_load(const Prm *p)
+{
+    const PDOT_GLOBAL uint64_t *src = gp((const uint64_t *)p);
+    uint64_t w[sizeof(Prm) / 8];
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(Prm) / 8); ++q)
+        w[q] = __hip_atomic_load(src + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    Prm P;
+    __builtin_memcpy(&P, w, sizeof(Prm));
+    return P;
+}
+
 // The combine kernel: one work-group per slice of 64 rows or 64 columns of an instance.
 //  1. adds the per-tile partial sums of the slice (the four waves split the partials; all
 //     loads of a wave are in flight together; fixed order);
@@ -1282,7 +1292,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
 
         // phase 3 (last work-group of the instance): reduce every record in a fixed order
         // and run the control
-        const Prm P = I.prm;
+        const Prm P = prm_load(&insts[E.inst].prm);
         const double tt = (double)(st.T + 1);
         const double g_red = pow(tt, -P.red_exp), g_grow = pow(tt, -P.grow_exp);
         double loc[kNB];

@@ -79,20 +79,25 @@ int lane_of(int64_t elems)
 
 // The widest lane (more bytes per load) whose tiles of 16 rows still number about four per
 // compute unit (1024); narrower lanes fill the GPU on mid-size instances (the autotuner
-// picks 1 column per lane for 1024 x 1024 grids and 4 for 4096 x 4096).
-int default_vec(int64_t m, int64_t n)
+// picks 1 column per lane for 1024 x 1024 grids and 4 for 4096 x 4096 with FP32 plans).
+// FP64 plans take at most 2 columns per lane: 4 doubles per lane and stream cost more
+// registers than they save (at 4096 x 4096, 91 us per pass with 2 columns and 64 rows
+// against 99 us with 4 and 64).
+int default_vec(int64_t m, int64_t n, bool fp32)
 {
     const int64_t rb = (m + 15) / 16;
-    for (int v = 4; v >= 2; v /= 2)
+    for (int v = fp32 ? 4 : 2; v >= 2; v /= 2)
         if (n >= 64 * v && rb * ((n + 64 * v - 1) / (64 * v)) >= 1024) return v;
     return 1;
 }
 
-int default_rows(int64_t m, int ncb)
+int default_rows(int64_t m, int ncb, bool fp32)
 {
-    // aim for about four tiles per compute unit on large instances while keeping the column
-    // partials (one row of n values per row block) small against the plan
-    int64_t r = (m * ncb + 1023) / 1024;
+    // aim for about four tiles per compute unit on large instances (eight with FP64 plans,
+    // whose lanes are narrower) while keeping the column partials (one row of n values per
+    // row block) small against the plan
+    const int64_t target = fp32 ? 1024 : 2048;
+    int64_t r = (m * ncb + target - 1) / target;
     r = std::max<int64_t>(16, std::min<int64_t>(256, r));
     r = (r + 15) / 16 * 16;
     return (int)r;
@@ -147,12 +152,12 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     const int64_t elems = pb.m * pb.n;
     L.resident = (prm.engine == 0 && elems <= OT_RESIDENT_MAX_ELEMS) ||
                  (prm.engine == 2 && elems <= OT_RESIDENT_HARD_MAX_ELEMS);
-    L.vec = pb.tile_vec > 0 ? pb.tile_vec : (prm.tile_vec ? prm.tile_vec : default_vec(pb.m, pb.n));
+    L.vec = pb.tile_vec > 0 ? pb.tile_vec : (prm.tile_vec ? prm.tile_vec : default_vec(pb.m, pb.n, L.fp32));
     if (L.vec != 1 && L.vec != 2 && L.vec != 4) return fail(OT_ERR_INVALID, "tile_vec must be 1, 2 or 4");
     // the resident kernel has no 4-column variant (it would spill registers)
     if (L.resident && L.vec == 4) L.vec = 2;
     L.ncb = (int)((pb.n + 64 * L.vec - 1) / (64 * L.vec));
-    L.rows = pb.tile_rows > 0 ? pb.tile_rows : (prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb));
+    L.rows = pb.tile_rows > 0 ? pb.tile_rows : (prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb, L.fp32));
     if (L.rows < 16 || L.rows % 16) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 16");
     // a resident instance is one row block: its work-group streams every row of a band
     if (L.resident) L.rows = (int)L.m_alloc;

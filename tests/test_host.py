@@ -39,6 +39,18 @@ def test_committed_cache_holds_valid_shapes():
         assert v["vec"] in (1, 2, 4) and v["rows"] >= 16 and v["rows"] % 16 == 0
 
 
+def test_committed_cache_covers_every_kind_and_precision():
+    """Both plan precisions and every cost kind the bench, batch and server use have tuned
+    shapes (images: every size bucket of the tuner)."""
+    cache = autotune.load_cache()
+    for prec in (0, 1):
+        for kind in autotune.KINDS:
+            keys = [k for k in cache if k.startswith(f"gfx950/p{prec}/{kind}/")]
+            assert keys, (prec, kind)
+            if kind in autotune.GRID_KINDS:
+                assert len(keys) == len(autotune.EXPS[kind])
+
+
 def test_bucket():
     assert autotune.bucket(32, 2048) == (5, 11)
     assert autotune.bucket(1, 1) == (0, 0)
