@@ -178,9 +178,9 @@ def summarize_traffic(fetch_dir, write_dir, probe_log):
         "",
         "Counters: `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch), each in its own run:",
         "",
-        f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_{tag} -o fetch -- python3 bench.py {flag} > gpurun_out/{tag}_probe.log 2>&1",
-        f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_{tag} -o write -- python3 bench.py {flag} > gpurun_out/{tag}_probe_w.log 2>&1",
-        f"    python3 bench.py --summarize-traffic gpurun_out/pmc_fetch_{tag} gpurun_out/pmc_write_{tag} gpurun_out/{tag}_probe.log",
+        f"    timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o fetch -- python3 bench.py {flag} > {probe_log} 2>&1",
+        f"    timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o write -- python3 bench.py {flag} > {os.path.join(os.path.dirname(probe_log), tag + '_probe_w.log')} 2>&1",
+        f"    python3 bench.py --summarize-traffic {fetch_dir} {write_dir} {probe_log}",
         "",
         "Calibration: a plain 1 GiB device copy reads {:.0f} and writes {:.0f} counter units,".format(fc, wc),
         "so one unit is {:.1f} read bytes and {:.1f} written bytes.".format(kf, kw),
