@@ -74,6 +74,8 @@ ot_status check_params(const ot_params &prm);
 bool is_device_ptr(const void *p);
 // Descriptor of an instance whose workspace starts at `base` (device address).
 void init_inst(const Layout &l, char *base, double scale, const ot_params &prm, double tol, Inst &I);
+// Bytes of one m x n plan buffer of the instance.
+int64_t plan_bytes(const Layout &l);
 // Control block of an instance before its first slot.
 void init_ctl(const Layout &l, const ot_params &prm, double tol, Ctl &c);
 // Result of a finished instance from its final control block (st: its status).

@@ -258,11 +258,32 @@ __device__ __forceinline__ double wave_sum_to63(double v)
 
 // ------------------------------------------------------------------ streaming pass
 
-// Non-temporal vector store of VEC plan entries (16-byte pieces): the plan and the
-// average are written once per pass and read back only by the next pass.
+// Store of VEC plan entries.  Plans that outgrow the caches: non-temporal vector stores
+// (16-byte pieces); the plan and the average are written once per pass and read back only
+// by the next pass.  Solves whose plans together fit kWtMaxBytes (`wt`): stores at agent
+// scope, which write through the chiplet's L2, so the release at the end of the pass finds
+// no dirty plan lines to write back (at 1024 x 1024 an FP32 pass went from 7.8 to 6.9 us,
+// FP64 from 8.9 to 7.7 us).  Where the plans outgrow the caches such stores cost stream
+// rate (at 8100 x 8100, 4.6 against 2.3 TB/s; the 256-instance batch 11 % longer), hence
+// the limit.
 template <typename T, int N>
-__device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N])
+__device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N], bool wt)
 {
+    if (wt) {
+        if constexpr (sizeof(T) * N % 8 == 0) {
+            constexpr int W = (int)(sizeof(T) * N / 8);
+            uint64_t w[W];
+            __builtin_memcpy(w, o, sizeof(T) * N);
+#pragma unroll
+            for (int k = 0; k < W; ++k)
+                __hip_atomic_store(reinterpret_cast<PDOT_GLOBAL uint64_t *>(p) + k, w[k], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+#pragma unroll
+            for (int e = 0; e < N; ++e) __hip_atomic_store(p + e, o[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
     if constexpr (!PDOT_NT_STORES) {
         store_pack<T, N>(p, o);
     } else if constexpr (sizeof(T) * N >= 16) {
@@ -358,6 +379,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
     // wave index as a wave-uniform value, so row indices and per-row data stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t m = I.m, n = I.n, ld = I.ld;
+    const bool wthru = I.wt != 0;   // plan stores through L2 (small plans)
     const int64_t i0 = (int64_t)tl.rb * I.rows;
     const int64_t ie = min(I.m_alloc, i0 + (int64_t)I.rows);
     const int64_t jband = (int64_t)tl.cb * (64 * VEC);   // first column of the tile (uniform)
@@ -561,8 +583,8 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
             }
             if (active) {
                 const int64_t rowoff = i * ld + jband;
-                if constexpr (kTrial) store_pack_nt<TX, VEC>(Xt + rowoff + jl, xn_out);
-                if constexpr (kAvgOut) store_pack_nt<TX, VEC>(Xn + rowoff + jl, xb_out);
+                if constexpr (kTrial) store_pack_nt<TX, VEC>(Xt + rowoff + jl, xn_out, wthru);
+                if constexpr (kAvgOut) store_pack_nt<TX, VEC>(Xn + rowoff + jl, xb_out, wthru);
             }
             // keep one row's arithmetic together: bounds the live temporaries
             __builtin_amdgcn_sched_barrier(0);

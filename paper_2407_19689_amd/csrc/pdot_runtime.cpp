@@ -283,6 +283,11 @@ void init_inst(const Layout &l, char *b, double scale, const ot_params &prm, dou
     I.prm = device_params(prm, tol);
 }
 
+int64_t plan_bytes(const Layout &l)
+{
+    return (int64_t)l.m_alloc * l.ld * (int64_t)l.es;
+}
+
 void init_ctl(const Layout &l, const ot_params &prm, double tol, Ctl &c)
 {
     memset(&c, 0, sizeof(c));
@@ -502,6 +507,10 @@ public:
     ~Engine() { release(); }
 
     // Set up the stream and the arena.  ws: caller workspace (nullable).
+    // Plan stores through L2 for every instance admitted from now on: for a fixed set whose
+    // plans together fit kWtMaxBytes (the server, whose set changes, never sets it).
+    void set_write_through(bool on) { write_through_ = on; }
+
     ot_status init(const ot_params &prm, hipStream_t user_stream, size_t arena_bytes, void *ws,
                    size_t ws_bytes, int max_slots)
     {
@@ -849,6 +858,7 @@ private:
         Inst &I = r.I;
         init_inst(l, b, pb.cost.scale, prm_, r.tol, I);
         I.ctl = d_ctls() + r.slot;   // the control block lives in the engine's table
+        I.wt = write_through_ ? 1 : 0;
         const int64_t m = l.m, n = l.n;
 
         HIP_TRY(hipMemsetAsync(b, 0, l.bytes, s_));
@@ -1092,6 +1102,7 @@ private:
     ot_params prm_{};
     hipStream_t s_ = nullptr;
     bool own_stream_ = false, own_arena_ = false;
+    bool write_through_ = false;   // set_write_through
     char *base_ = nullptr;
     Arena arena_;
     int max_slots_ = 0;
@@ -1180,6 +1191,9 @@ ot_status run_fixed(const ot_problem *probs, int count, const ot_params &prm, ot
     }
     Engine E;
     OT_TRY(E.init(prm, stream, P.total, workspace, ws_bytes, count));
+    int64_t plans = 0;
+    for (int i = 0; i < count; ++i) plans += plan_bytes(P.L[i]);
+    E.set_write_through(plans <= kWtMaxBytes);
     for (int i = 0; i < count; ++i) {
         ot_status st = E.admit(reqs[i]);
         if (st != OT_OK)
