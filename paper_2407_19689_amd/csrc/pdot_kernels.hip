@@ -779,8 +779,8 @@ __device__ __forceinline__ void trace_put(Ctl &c, const TraceOut &to, int64_t pa
 }
 
 // Step-size check of the trial (Section 5, adaptive step size).
-// g_red = (T+1)^-a and g_grow = (T+1)^-b are evaluated by the caller (in parallel with
-// its loads) for the current T.
+// g_red = (T+1)^-a and g_grow = (T+1)^-b are evaluated by the caller (step_factors, on
+// other lanes) for the current T.
 // aux: <C, next average> of a pass that folded two iterates.
 // A rejected trial is traced at once; an accepted one when its KKT values and restart
 // decision are known (the next M_FULL control), from the fields kept in tr_*.
@@ -1169,6 +1169,19 @@ __device__ __forceinline__ void rec_take(PDOT_GLOBAL uint64_t *w, double (&v)[kN
     for (int q = 0; q < kNB; ++q) v[q] = b[q] ? __longlong_as_double((long long)(b[q] - 1u)) : 0.0;
 }
 
+// The step rule's factors (T+1)^-a and (T+1)^-b (Section 5), a pow each (about a hundred
+// FP64 instructions): evaluated by one lane of waves 1 and 2 and handed to the control
+// thread through LDS at the barrier that precedes it, so they run beside the other waves'
+// work instead of on the control thread's chain (the compiler would otherwise sink them
+// into the single thread that uses them).
+__device__ __forceinline__ void step_factors(double red_exp, double grow_exp, int64_t T, double *dst)
+{
+    if (threadIdx.x == 64 || threadIdx.x == 128) {
+        const double tt = (double)(T + 1);
+        dst[threadIdx.x == 128 ? 1 : 0] = pow(tt, -(threadIdx.x == 64 ? red_exp : grow_exp));
+    }
+}
+
 // The run parameters of an instance, with vector loads all in flight together.  Through
 // the scalar cache the control would fetch each field where it first uses it, one
 // dependent miss after another on the slot's critical path.
@@ -1201,6 +1214,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
     __shared__ double tsum[kNS];
     __shared__ double fin[4][kNB];
     __shared__ int is_last, lost_any;
+    __shared__ double gfac[2];   // step factors for the control thread
     if (threadIdx.x == 0) lost_any = 0;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1315,8 +1329,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
         // phase 3 (last work-group of the instance): reduce every record in a fixed order
         // and run the control
         const Prm P = prm_load(&insts[E.inst].prm);
-        const double tt = (double)(st.T + 1);
-        const double g_red = pow(tt, -P.red_exp), g_grow = pow(tt, -P.grow_exp);
+        step_factors(P.red_exp, P.grow_exp, st.T, gfac);
         double loc[kNB];
 #pragma unroll
         for (int q = 0; q < kNB; ++q) loc[q] = 0.0;
@@ -1347,7 +1360,7 @@ __global__ __launch_bounds__(kWG) void k_combine(const Inst *__restrict__ insts,
                 c.status = ST_DEVICE;
                 c.mode = M_IDLE;
             } else {
-                control(c, P, mode, tot, tot + kNC, g_red, g_grow, TraceOut{I.trace, I.trace_cap});
+                control(c, P, mode, tot, tot + kNC, gfac[0], gfac[1], TraceOut{I.trace, I.trace_cap});
             }
             gp(ctls)[E.inst] = c;
             __hip_atomic_store(gp(I.counter), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1399,6 +1412,7 @@ void k_resident(const Inst *__restrict__ insts, const int32_t *__restrict__ list
     const int nres = *cp(count);
     __shared__ double lds[3 * 2 * 4 * 64 + 4 * kNS];
     __shared__ double red[4][kNB];
+    __shared__ double gfac[2];   // step factors for the control thread
     __shared__ Ctl sctl;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1450,16 +1464,15 @@ void k_resident(const Inst *__restrict__ insts, const int32_t *__restrict__ list
 #pragma unroll
                 for (int q = 0; q < kNB; ++q) red[wave][q] = r[q];
             }
+            step_factors(I.prm.red_exp, I.prm.grow_exp, st.T, gfac);
             __syncthreads();
             if (threadIdx.x == 0) {
                 const Prm P = I.prm;
-                const double tt = (double)(st.T + 1);
                 double tot[kNB];
                 for (int q = 0; q < kNB; ++q)
                     tot[q] = ((red[0][q] + red[1][q]) + red[2][q]) + red[3][q];
                 Ctl c = sctl;
-                control(c, P, mode, tot, tot + kNC, pow(tt, -P.red_exp), pow(tt, -P.grow_exp),
-                        TraceOut{I.trace, I.trace_cap});
+                control(c, P, mode, tot, tot + kNC, gfac[0], gfac[1], TraceOut{I.trace, I.trace_cap});
                 sctl = c;
             }
             __syncthreads();
