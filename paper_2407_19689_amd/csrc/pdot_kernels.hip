@@ -1142,31 +1142,31 @@ __device__ __forceinline__ void rec_clear(PDOT_GLOBAL uint64_t *w)
     *w = 0;
 }
 
-// Take the kNB words of one record: all loads in flight together (the words normally
-// arrived before the writer moved the counter), then a wait for any word still zero
-// (bounded: after kRecSpin loads `lost` is set and the caller stops the instance with a
-// device error instead of waiting on).
+// Take the kNB words of one record: all loads in flight together, then, while any word is
+// still zero, a short sleep and the zero words loaded again, all together (bounded: after
+// kRecSpin rounds `lost` is set and the caller stops the instance with a device error
+// instead of waiting on).
 constexpr int kRecSpin = 1 << 20;
 __device__ __forceinline__ void rec_take(PDOT_GLOBAL uint64_t *w, double (&v)[kNB], bool &lost)
 {
     uint64_t b[kNB];
 #pragma unroll
     for (int q = 0; q < kNB; ++q) b[q] = __hip_atomic_load(w + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    bool all = true;
+    for (int k = 0; k < kRecSpin; ++k) {
+        bool all = true;
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) all = all && b[q] != 0;
-    if (!all) {
+        for (int q = 0; q < kNB; ++q) all = all && b[q] != 0;
+        if (all) break;
+        __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-        for (int q = 0; q < kNB; ++q) {
-            for (int k = 0; b[q] == 0 && k < kRecSpin; ++k) {
-                __builtin_amdgcn_s_sleep(1);
-                b[q] = __hip_atomic_load(w + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (b[q] == 0) lost = true;
-        }
+        for (int q = 0; q < kNB; ++q)
+            if (b[q] == 0) b[q] = __hip_atomic_load(w + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 #pragma unroll
-    for (int q = 0; q < kNB; ++q) v[q] = b[q] ? __longlong_as_double((long long)(b[q] - 1u)) : 0.0;
+    for (int q = 0; q < kNB; ++q) {
+        if (b[q] == 0) lost = true;
+        v[q] = b[q] ? __longlong_as_double((long long)(b[q] - 1u)) : 0.0;
+    }
 }
 
 // The step rule's factors (T+1)^-a and (T+1)^-b (Section 5), a pow each (about a hundred
