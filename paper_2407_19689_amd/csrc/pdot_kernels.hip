@@ -265,24 +265,27 @@ __device__ __forceinline__ double wave_sum_to63(double v)
 // no dirty plan lines to write back (at 1024 x 1024 an FP32 pass went from 7.8 to 6.9 us,
 // FP64 from 8.9 to 7.7 us).  Where the plans outgrow the caches such stores cost stream
 // rate (at 8100 x 8100, 4.6 against 2.3 TB/s; the 256-instance batch 11 % longer), hence
-// the limit.
+// the limit.  Only the narrow lanes (under 16 bytes of plan per lane) have the write-through
+// path: a solve whose plans fit the limit gets them by default, and the 16-byte variants
+// that stream the large plans keep their code as it was (the branch alone cost 1.7 % at
+// 4096 x 4096).
 template <typename T, int N>
 __device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N], bool wt)
 {
-    if (wt) {
-        if constexpr (sizeof(T) * N % 8 == 0) {
-            constexpr int W = (int)(sizeof(T) * N / 8);
-            uint64_t w[W];
-            __builtin_memcpy(w, o, sizeof(T) * N);
-#pragma unroll
-            for (int k = 0; k < W; ++k)
-                __hip_atomic_store(reinterpret_cast<PDOT_GLOBAL uint64_t *>(p) + k, w[k], __ATOMIC_RELAXED,
+    if constexpr (sizeof(T) * N < 16) {
+        if (wt) {
+            if constexpr (sizeof(T) * N == 8) {
+                uint64_t w;
+                __builtin_memcpy(&w, o, 8);
+                __hip_atomic_store(reinterpret_cast<PDOT_GLOBAL uint64_t *>(p), w, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+            } else {
 #pragma unroll
-            for (int e = 0; e < N; ++e) __hip_atomic_store(p + e, o[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int e = 0; e < N; ++e)
+                    __hip_atomic_store(p + e, o[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            return;
         }
-        return;
     }
     if constexpr (!PDOT_NT_STORES) {
         store_pack<T, N>(p, o);
