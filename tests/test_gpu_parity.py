@@ -682,3 +682,28 @@ def test_caller_workspace_and_stream():
     small = torch.empty(nbytes // 2, dtype=torch.uint8, device="cuda")
     st, _ = P.ot_solve(pr, prm, workspace=small)
     assert st == P.OT_ERR_OOM
+
+
+@pytest.mark.parametrize("prec", [P.OT_PREC_FP32, P.OT_PREC_FP64])
+def test_write_through_plan_stores_change_no_value(prec):
+    """A solve whose plans fit 8 MB stores them through L2 (agent-scope stores); the same
+    1024 x 1024 instance solved in a batch beside a 2304 x 2304 one (plans over the limit,
+    ordinary stores) gives the same iterates bit for bit, and both match the oracle."""
+    small = gen.grid_pair(46, 32, tol=1e-5)
+    big = gen.grid_pair(47, 48, tol=1e-4)
+    prm = P.params(tol=1e-5, precision=prec, time_limit_s=60.0)
+    s1, r1, o1 = P.solve_instance(small, prm, tol=small.tol)
+    assert s1 == P.OT_OK
+    probs, outs = [], []
+    for inst in (small, big):
+        pr, out = P.problem_from_instance(inst, precision=prec, tol=inst.tol)
+        probs.append(pr)
+        outs.append(out)
+    st, results = P.ot_solve_batch(probs, prm)
+    torch.cuda.synchronize()
+    assert st == P.OT_OK, P.ot_last_error()
+    assert results[0].iterations == r1["iterations"]
+    assert np.array_equal(outs[0]["X"].cpu().numpy(), o1["X"].cpu().numpy())
+    assert np.array_equal(outs[0]["u"].cpu().numpy(), o1["u"].cpu().numpy())
+    assert np.array_equal(outs[0]["v"].cpu().numpy(), o1["v"].cpu().numpy())
+    assert_matches_oracle(small, r1, o1, prec)
