@@ -91,12 +91,16 @@ int default_vec(int64_t m, int64_t n, bool fp32)
     return 1;
 }
 
-int default_rows(int64_t m, int ncb, bool fp32)
+int default_rows(int64_t m, int ncb, bool fp32, int vec, bool points)
 {
     // aim for about four tiles per compute unit on large instances (eight with FP64 plans,
     // whose lanes are narrower) while keeping the column partials (one row of n values per
-    // row block) small against the plan
-    const int64_t target = fp32 ? 1024 : 2048;
+    // row block) small against the plan.  The 4-column FP32 kernel of the grid and stored
+    // costs runs three work-groups per compute unit (165 VGPRs), so it aims for one full
+    // round of them (768 tiles): at 4096 x 4096, 96-row tiles (688) instead of 64-row ones
+    // (1024, 1.33 rounds) took 47.7 against 51.2 us per pass and 4.4 % less time to 1e-6
+    // over 25 images (seeds 200-224; iteration counts equal within 3 %).
+    const int64_t target = !fp32 ? 2048 : (vec == 4 && !points ? 768 : 1024);
     int64_t r = (m * ncb + target - 1) / target;
     r = std::max<int64_t>(16, std::min<int64_t>(256, r));
     r = (r + 15) / 16 * 16;
@@ -157,7 +161,7 @@ ot_status plan_instance(const ot_problem &pb, const ot_params &prm, Layout &L)
     // the resident kernel has no 4-column variant (it would spill registers)
     if (L.resident && L.vec == 4) L.vec = 2;
     L.ncb = (int)((pb.n + 64 * L.vec - 1) / (64 * L.vec));
-    L.rows = pb.tile_rows > 0 ? pb.tile_rows : (prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb, L.fp32));
+    L.rows = pb.tile_rows > 0 ? pb.tile_rows : (prm.tile_rows ? prm.tile_rows : default_rows(pb.m, L.ncb, L.fp32, L.vec, L.cost == C_PTS_SQ || L.cost == C_PTS_EU));
     if (L.rows < 16 || L.rows % 16) return fail(OT_ERR_INVALID, "tile_rows must be a positive multiple of 16");
     // a resident instance is one row block: its work-group streams every row of a band
     if (L.resident) L.rows = (int)L.m_alloc;
