@@ -45,7 +45,8 @@ constexpr int kCombEntries = 64;  // rows or columns handled by one combine work
 constexpr int kNS = 6;            // per-tile scalars
 constexpr int kNC = 8;            // per-combine-entry scalars
 constexpr int kNB = kNC + kNS;
-constexpr int64_t kWtMaxBytes = (int64_t)8 << 20;   // largest plans stored through L2    // combine record: entry scalars, then its share of tile scalars
+constexpr int64_t kWtMaxBytes = (int64_t)8 << 20;         // narrow write-through: plans together
+constexpr int64_t kWtMinWideBytes = (int64_t)128 << 20;   // wide write-through: one plan    // combine record: entry scalars, then its share of tile scalars
 
 // scalars of the rounding passes (in combscal of the rounding instance)
 enum { RD_MARG = 0, RD_L1 = 1, RD_UPPER = 2, RD_CHANGE = 3, RD_LOWER = 4, RD_VIOL = 5 };
@@ -108,7 +109,8 @@ struct Inst {
     int32_t cost, dim, side, vec;
     int32_t rows, ncb, nrb, ntiles;
     int32_t ncomb;
-    int32_t wt;             // plan stores write through L2 (a solve whose plans fit kWtMaxBytes)
+    int32_t wt;             // write-through plan stores: 1 narrow lanes of a solve whose plans
+                            // fit kWtMaxBytes, 2 wide lanes of a plan of kWtMinWideBytes or more
     double scale;
     void *X[kBufs];
     const void *C;          // stored cost in the working precision (C_STORED)

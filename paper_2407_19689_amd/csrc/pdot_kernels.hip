@@ -258,22 +258,25 @@ __device__ __forceinline__ double wave_sum_to63(double v)
 
 // ------------------------------------------------------------------ streaming pass
 
-// Store of VEC plan entries.  Plans that outgrow the caches: non-temporal vector stores
-// (16-byte pieces); the plan and the average are written once per pass and read back only
-// by the next pass.  Solves whose plans together fit kWtMaxBytes (`wt`): stores at agent
-// scope, which write through the chiplet's L2, so the release at the end of the pass finds
-// no dirty plan lines to write back (at 1024 x 1024 an FP32 pass went from 7.8 to 6.9 us,
-// FP64 from 8.9 to 7.7 us).  Where the plans outgrow the caches such stores cost stream
-// rate (at 8100 x 8100, 4.6 against 2.3 TB/s; the 256-instance batch 11 % longer), hence
-// the limit.  Only the narrow lanes (under 16 bytes of plan per lane) have the write-through
-// path: a solve whose plans fit the limit gets them by default, and the 16-byte variants
-// that stream the large plans keep their code as it was (the branch alone cost 1.7 % at
-// 4096 x 4096).
+// Store of VEC plan entries: non-temporal vector stores (16-byte pieces) by default; the
+// plan and the average are written once per pass and read back only by the next pass.
+// Two write-through forms (Inst::wt), which leave no dirty plan lines in the chiplet's L2:
+//  * WT_NARROW, solves whose plans together fit kWtMaxBytes, on lanes of under 16 bytes:
+//    agent-scope word stores, so the release at the end of the pass has nothing to write
+//    back (at 1024 x 1024 an FP32 pass went from 7.8 to 6.9 us, FP64 from 8.9 to 7.7 us).
+//    On plans beyond the caches word stores halve the stream rate (at 8100 x 8100, 4.6
+//    against 2.3 TB/s), hence the limit.
+//  * WT_WIDE, plans of at least kWtMinWideBytes (beyond the Infinity Cache), on 16-byte
+//    lanes: buffer stores with the device-scope and non-temporal bits (the buffer
+//    descriptor's base is the row's first entry, uniform across the wave), 4.75 against
+//    4.48 TB/s at 8100 x 8100.  On plans the Infinity Cache still holds they cost a third
+//    of the rate (at 4096 x 4096, 46 against 34 us per pass), hence the floor.
+enum { WT_NARROW = 1, WT_WIDE = 2 };
 template <typename T, int N>
-__device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N], bool wt)
+__device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, const T (&o)[N], int wt)
 {
     if constexpr (sizeof(T) * N < 16) {
-        if (wt) {
+        if (wt & WT_NARROW) {
             if constexpr (sizeof(T) * N == 8) {
                 uint64_t w;
                 __builtin_memcpy(&w, o, 8);
@@ -292,6 +295,28 @@ __device__ __forceinline__ void store_pack_nt(PDOT_GLOBAL T *__restrict__ p, con
     } else if constexpr (sizeof(T) * N >= 16) {
         constexpr int E = 16 / sizeof(T);   // entries per 16-byte piece
         typedef T V __attribute__((ext_vector_type(E)));
+        if (wt & WT_WIDE) {
+            typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+            // the lanes of a wave store one row of the tile: descriptor base = its first
+            // entry (the same for every lane), bounds = the row's 64 * N entries
+            const int ln = threadIdx.x & 63;
+            const uint64_t a = (uint64_t)(uintptr_t)(p - ln * N);
+            const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+            const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(uintptr_t)(((uint64_t)hi << 32) | lo), (short)0, 64 * N * (int)sizeof(T), 0x00020000);
+#pragma unroll
+            for (int c = 0; c < N / E; ++c) {
+                V v;
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = o[c * E + e];
+                U4 u;
+                __builtin_memcpy(&u, &v, 16);
+                __builtin_amdgcn_raw_buffer_store_b128(u, rs, (ln * N + c * E) * (int)sizeof(T), 0,
+                                                       16 /* device scope */ | 2 /* non-temporal */);
+            }
+            return;
+        }
 #pragma unroll
         for (int c = 0; c < N / E; ++c) {
             V v;
@@ -382,7 +407,7 @@ __device__ void tile_body(const PDOT_CONST Inst &I, const Ctl &st, const Tile &t
     // wave index as a wave-uniform value, so row indices and per-row data stay scalar
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t m = I.m, n = I.n, ld = I.ld;
-    const bool wthru = I.wt != 0;   // plan stores through L2 (small plans)
+    const int wthru = I.wt;   // write-through plan stores (WT_NARROW, WT_WIDE)
     const int64_t i0 = (int64_t)tl.rb * I.rows;
     const int64_t ie = min(I.m_alloc, i0 + (int64_t)I.rows);
     const int64_t jband = (int64_t)tl.cb * (64 * VEC);   // first column of the tile (uniform)

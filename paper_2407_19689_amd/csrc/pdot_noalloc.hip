@@ -142,7 +142,7 @@ ot_status solve_noalloc(const ot_problem &pb, const ot_params &prm, ot_result *r
     const int64_t m = L.m, n = L.n;
     Inst I;
     init_inst(L, ws, pb.cost.scale, prm, tol, I);
-    I.wt = plan_bytes(L) <= kWtMaxBytes ? 1 : 0;
+    I.wt = (plan_bytes(L) <= kWtMaxBytes ? 1 : 0) | (plan_bytes(L) >= kWtMinWideBytes ? 2 : 0);
     NA_TRY(launch_zero(ws, L.bytes, s));
     NA_TRY(hipMemcpyAsync((void *)I.f, pb.f, sizeof(double) * m, hipMemcpyDefault, s));
     NA_TRY(hipMemcpyAsync((void *)I.g, pb.g, sizeof(double) * n, hipMemcpyDefault, s));

@@ -511,7 +511,8 @@ public:
     ~Engine() { release(); }
 
     // Set up the stream and the arena.  ws: caller workspace (nullable).
-    // Plan stores through L2 for every instance admitted from now on: for a fixed set whose
+    // Narrow write-through plan stores (WT_NARROW) for every instance admitted from now on:
+    // for a fixed set whose
     // plans together fit kWtMaxBytes (the server, whose set changes, never sets it).
     void set_write_through(bool on) { write_through_ = on; }
 
@@ -862,7 +863,7 @@ private:
         Inst &I = r.I;
         init_inst(l, b, pb.cost.scale, prm_, r.tol, I);
         I.ctl = d_ctls() + r.slot;   // the control block lives in the engine's table
-        I.wt = write_through_ ? 1 : 0;
+        I.wt = (write_through_ ? 1 : 0) | (plan_bytes(l) >= kWtMinWideBytes ? 2 : 0);
         const int64_t m = l.m, n = l.n;
 
         HIP_TRY(hipMemsetAsync(b, 0, l.bytes, s_));
